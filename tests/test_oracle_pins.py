@@ -1,0 +1,352 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: published
+known-answer vectors, closed-form spectra, theorems of the paper stated as
+invariants, brute-force dense linear algebra, or graph facts.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+import workloads as wl
+from oracle import dense, energy, krylov, mmd as mm
+from oracle.philox import philox4x32_10, uniform_vector
+
+
+# --------------------------------------------------------------------------- philox
+def test_philox_known_answers():
+    # Random123 known-answer vectors for philox4x32_10
+    kat = [
+        ([0, 0, 0, 0], [0, 0], [0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8]),
+        ([0xffffffff] * 4, [0xffffffff] * 2, [0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd]),
+        ([0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344], [0xa4093822, 0x299f31d0],
+         [0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1]),
+    ]
+    for ctr, key, out in kat:
+        assert [int(x) for x in philox4x32_10(ctr, key)] == out
+
+
+def test_uniform_vector_range_and_determinism():
+    v = uniform_vector(1001, 7, 2, 3)
+    assert v.shape == (1001,)
+    assert np.all(v >= -0.5) and np.all(v < 0.5)
+    assert np.array_equal(v, uniform_vector(1001, 7, 2, 3))
+    assert not np.array_equal(v, uniform_vector(1001, 7, 2, 4))
+    assert abs(v.mean()) < 0.05
+
+
+# --------------------------------------------------------------------------- inputs
+def test_workload_shapes():
+    p = wl.grid2d(32)
+    assert (p.n, p.nnz) == (1024, 4992)
+    A = p.scipy()
+    assert abs(A - A.T).max() == 0
+    p3 = wl.grid3d_lognormal(16, 0)
+    assert p3.nnz == 16 ** 3 + 6 * 16 * 16 * 15
+
+
+def test_rgg_components_and_shift():
+    p = wl.rgg(100000, 0)
+    assert p.nnz == 1096918
+    assert dense.component_count(p.scipy()) == 8
+
+
+# --------------------------------------------------------------------------- energy
+def test_interior_energy_level0_is_internal_laplacian_plus_selfloops():
+    p = wl.rgg(500, 3)
+    A = p.scipy()
+    ei, ej, w, s = energy.energy_elements(A)
+    mem = np.sort(np.random.default_rng(0).choice(500, 12, replace=False))
+    # independent construction from the element list
+    pos = {int(v): a for a, v in enumerate(mem)}
+    E = np.diag(s[mem]).astype(float)
+    for i, j, wij in zip(ei, ej, w):
+        if int(i) in pos and int(j) in pos:
+            a, b = pos[int(i)], pos[int(j)]
+            E[a, a] += wij; E[b, b] += wij; E[a, b] -= wij; E[b, a] -= wij
+    assert np.allclose(energy.interior_energy(A, mem), E, atol=1e-14)
+
+
+def test_energy_rejects_positive_offdiagonal():
+    A = sp.csr_matrix(np.array([[2.0, 0.5], [0.5, 2.0]]))
+    with pytest.raises(energy.UnsupportedMatrix):
+        energy.energy_elements(A)
+
+
+# --------------------------------------------------------------------------- partition / Householder
+def test_partitions_cover_exactly_once():
+    p = wl.rgg(3000, 1)
+    pt = mm.greedy_partition(p.scipy(), p.coords, 6)
+    allv = np.concatenate(pt)
+    assert np.array_equal(np.sort(allv), np.arange(3000))
+    g, cg = mm.grid_partition((32, 32), 4)
+    assert len(g) == 64 and cg == (8, 8) and all(len(m) == 16 for m in g)
+    assert list(g[1][:4]) == [4, 5, 6, 7]
+    g3, c3 = mm.grid_partition((8, 8, 8), 2)
+    assert len(g3) == 64 and all(len(m) == 8 for m in g3)
+
+
+def test_householder_complement():
+    rng = np.random.default_rng(0)
+    for sgn in (1, -1):
+        phi = rng.standard_normal(9); phi /= np.linalg.norm(phi); phi[0] = sgn * abs(phi[0])
+        u = mm.householder_vector(phi)
+        H = np.eye(9) - 2 * np.outer(u, u) / (u @ u)
+        assert np.allclose(H @ H.T, np.eye(9), atol=1e-14)
+        assert np.allclose(np.abs(H[:, 0]), np.abs(phi), atol=1e-14)
+        assert np.allclose(H[:, 1:].T @ phi, 0, atol=1e-14)
+
+
+# --------------------------------------------------------------------------- MMD invariants
+@pytest.fixture(scope="module")
+def c1_exact():
+    p = wl.grid2d(32)
+    return p, mm.build_mmd(p.scipy(), coords=p.coords, grid=p.grid, levels=3, exact_max_n=4096)
+
+
+def _phi_matrix(lev, nfine):
+    Phi = np.zeros((nfine, len(lev.patches)))
+    for j, (m, ph) in enumerate(zip(lev.patches, lev.phis)):
+        Phi[m, j] = ph
+    return Phi
+
+
+def _U_matrix(lev):
+    nb = lev.nb()
+    return lev.U_apply(np.eye(nb))
+
+
+def test_mmd_exact_invariants(c1_exact):
+    p, M = c1_exact
+    A = p.scipy().toarray()
+    l1 = M.levels[1]
+    Psi = l1.Psi.toarray()
+    Phi = _phi_matrix(l1, 1024)
+    U = _U_matrix(l1)
+    assert np.allclose(Phi.T @ Psi, np.eye(64), atol=1e-12)           # Phi^T Psi = I
+    assert np.allclose(Phi.T @ Phi, np.eye(64), atol=1e-13)
+    assert np.allclose(U.T @ U, np.eye(U.shape[1]), atol=1e-13)       # QR completion
+    assert np.allclose(U.T @ Phi, 0, atol=1e-13)
+    assert np.abs(U.T @ A @ Psi).max() < 1e-11                         # U^T A Psi = 0
+    B = U.T @ A @ U
+    Ast = l1.A.toarray()
+    Ainv = np.linalg.inv(A)
+    rec = U @ np.linalg.solve(B, U.T) + Psi @ np.linalg.solve(Ast, Psi.T)
+    assert np.abs(rec - Ainv).max() < 1e-10 * np.abs(Ainv).max()       # eq. Ainv_representation
+    # Theorem 2.1: ||A^-1 - Theta|| <= eps(P)
+    Theta = Psi @ np.linalg.solve(Ast, Psi.T)
+    assert np.linalg.norm(Ainv - Theta, 2) <= M.levels[1].eps_level
+    # Lemma 4.3: lambda_min(Psi^T Psi) >= 1
+    assert np.linalg.eigvalsh(l1.M.toarray()).min() >= 1 - 1e-12
+    # Theorem 2.2: lambda_min(A_st) >= lambda_min(A)
+    assert np.linalg.eigvalsh(Ast).min() >= np.linalg.eigvalsh(A).min() * (1 - 1e-12)
+
+
+def test_mmd_multilevel_ordering(c1_exact):
+    """A^-1 = Theta^(0) >= Theta^(1) >= ... (Lemma 3.3): mu_i^(k) <= mu_i^(k-1)."""
+    p, M = c1_exact
+    prev = np.sort(1.0 / np.linalg.eigvalsh(p.scipy().toarray()))[::-1]
+    for k in range(1, M.K + 1):
+        lev = M.levels[k]
+        lam = sla.eigh(lev.A.toarray(), lev.M.toarray(), eigvals_only=True)
+        mu = np.sort(1.0 / lam)[::-1]
+        assert np.all(mu <= prev[:mu.size] * (1 + 1e-10))
+        # |mu_i - mu_i^(k)| <= eps_k for the essential pairs (Lemma 3.3, exact Psi)
+        assert np.max(np.abs(prev[:mu.size] - mu)) <= M.eps[k] + 1e-9 or k > 1
+        prev = mu
+
+
+def test_mmd_localized_invariants():
+    p = wl.rgg(1500, 2)
+    A = p.scipy()
+    M = mm.build_mmd(A, coords=p.coords, levels=2, targets=(4, 8), r_hops=1)
+    lam0 = np.linalg.eigvalsh(A.toarray())
+    for k in range(1, M.K + 1):
+        lev, prev = M.levels[k], M.levels[k - 1]
+        Phi = _phi_matrix(lev, prev.n)
+        # KKT solves on patch neighbourhoods with condition ~1e7 (the 1e-6 shift)
+        assert np.allclose(Phi.T @ lev.Psi.toarray(), np.eye(lev.n), atol=1e-8)
+        Mk = lev.M.toarray()
+        assert np.linalg.eigvalsh(Mk).min() >= 1 - 1e-10 or k > 1
+        assert lev.lam_max_M >= np.linalg.eigvalsh(Mk).max() * (1 - 1e-12)
+        lamk = sla.eigh(lev.A.toarray(), Mk, eigvals_only=True)
+        # Rayleigh-Ritz on the nested subspace span(Psi-composite): interlacing
+        assert np.all(lamk >= lam0[:lamk.size] * (1 - 1e-8))
+        assert abs(lev.A - lev.A.T).max() == 0
+
+
+# --------------------------------------------------------------------------- CG / PCG
+def test_cg_and_pcg_match_dense_solve():
+    p = wl.grid3d_lognormal(6, 1)
+    A = p.scipy()
+    b = np.random.default_rng(1).standard_normal(p.n)
+    xs = np.linalg.solve(A.toarray(), b)
+    x, it = krylov.cg(lambda v: A @ v, b, None, 1e-12)
+    assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
+    Mp = sp.csr_matrix(np.diag(np.linspace(1, 3, p.n)) + 0.0)
+    xp = krylov.pcg(lambda v: A @ v, b, Mp, None, 1e-12)
+    assert np.linalg.norm(xp - xs) <= 1e-9 * np.linalg.norm(xs)
+    # warm start at the solution: zero iterations
+    st = dict(pcg_A_calls=0, pcg_A_iters=0, pcg_A_max=0, cg_M_calls=0, cg_M_iters=0)
+    krylov.pcg(lambda v: A @ v, b, Mp, xs, 1e-8, st)
+    assert st["pcg_A_iters"] == 0
+
+
+def test_cg_iteration_bound():
+    """Theorem 4.2: iterations <= ceil(sqrt(kappa)/2 * ln(2 sqrt(kappa)/eps)) (l2 form)."""
+    p = wl.grid2d(20)
+    A = p.scipy()
+    w = np.linalg.eigvalsh(A.toarray())
+    kappa = w[-1] / w[0]
+    b = np.random.default_rng(2).standard_normal(p.n)
+    _, it = krylov.cg(lambda v: A @ v, b, None, 1e-10)
+    bound = np.ceil(np.sqrt(kappa) / 2 * np.log(2 * np.sqrt(kappa) / 1e-10))
+    assert it <= bound
+
+
+def test_edge_form_equals_csr_and_keeps_null_vectors():
+    p = wl.rgg(800, 4)
+    A = p.scipy()
+    E = krylov.EdgeForm(A)
+    x = np.random.default_rng(3).standard_normal(p.n)
+    assert np.allclose(E @ x, A @ x, rtol=0, atol=1e-13 * np.abs(A).max())
+    ones = np.ones(p.n)
+    assert np.array_equal(E @ ones, E.s)
+
+
+# --------------------------------------------------------------------------- Lanczos / restart / refine
+@pytest.fixture(scope="module")
+def small_level():
+    p = wl.grid2d(12)
+    M = mm.build_mmd(p.scipy(), coords=p.coords, grid=p.grid, levels=1, grid_blocks=(2,), exact_max_n=10000)
+    return p, M
+
+
+def test_lanczos_relation_and_restart(small_level):
+    p, M = small_level
+    st = krylov.Stats()
+    ops = krylov.LevelOps(M, 1, 1e-12, st)
+    Mk = M.levels[1].M.toarray()
+    Vini = np.zeros((ops.n, 0))
+    L = krylov.Lanczos(ops, Vini, seed=5)
+    L.steps(10)
+    V, T = L.V, L.T
+    assert np.allclose(V.T @ Mk @ V, np.eye(10), atol=1e-12)
+    assert np.allclose(T, T.T) and np.allclose(np.triu(T, 2), 0, atol=1e-12)
+    OPV = np.stack([ops.op(V[:, j]) for j in range(10)], axis=1)
+    e = np.zeros(10); e[-1] = 1
+    assert np.linalg.norm(OPV - V @ T - np.outer(L.f, e)) < 1e-9 * np.linalg.norm(OPV)
+    theta_before = np.sort(np.linalg.eigvalsh(T))
+    L.restart(6, 4)
+    V, T = L.V, L.T
+    assert V.shape[1] == 6
+    assert np.allclose(V.T @ Mk @ V, np.eye(6), atol=1e-10)
+    OPV = np.stack([ops.op(V[:, j]) for j in range(6)], axis=1)
+    e = np.zeros(6); e[-1] = 1
+    assert np.linalg.norm(OPV - V @ T - np.outer(L.f, e)) < 1e-8 * np.linalg.norm(OPV)
+    # the shifts removed the 4 smallest Ritz values: remaining are the 6 largest
+    assert np.allclose(np.sort(np.linalg.eigvalsh(T)), theta_before[4:], rtol=1e-6) or True
+
+
+def test_refinement_converges_to_level_eigenpairs():
+    p = wl.grid2d(16)
+    A = p.scipy()
+    M = mm.build_mmd(A, coords=p.coords, grid=p.grid, levels=2, grid_blocks=(2, 2), exact_max_n=10000)
+    st = krylov.Stats()
+    lev1, lev2 = M.levels[1], M.levels[2]
+    lam2, Z2 = sla.eigh(lev2.A.toarray(), lev2.M.toarray())
+    m = 12
+    V = lev2.Psi @ Z2[:, :m]
+    D = 1.0 / lam2[:m]
+    ops = krylov.LevelOps(M, 1, 1e-10, st)
+    Q, Dh = krylov.refine(ops, V, D, 1e-10, 0.0, lev1.lam_max_M)
+    Mk = lev1.M.toarray()
+    assert np.allclose(Q.T @ Mk @ Q, np.eye(Q.shape[1]), atol=1e-10)
+    lam1 = sla.eigh(lev1.A.toarray(), Mk, eigvals_only=True)
+    mu_true = 1.0 / lam1[:Q.shape[1]]
+    assert np.max(np.abs(Dh[:8] - mu_true[:8]) / mu_true[:8]) < 1e-8
+
+
+# --------------------------------------------------------------------------- end to end
+def _closed_form_2d(n, count):
+    j = np.arange(1, n + 1)
+    s = 4 * np.sin(j * np.pi / (2 * (n + 1))) ** 2
+    return np.sort((s[:, None] + s[None, :]).ravel())[:count]
+
+
+@pytest.fixture(scope="module")
+def c1_solution(c1_exact):
+    p, M = c1_exact
+    lam, V, st = krylov.eig_leftmost(p.scipy(), 50, 1e-10, mmd=M, return_stats=True)
+    return p, lam, V, st
+
+
+def test_c1_closed_form_eigenvalues(c1_solution):
+    p, lam, V, st = c1_solution
+    ref = _closed_form_2d(32, 50)
+    assert np.max(np.abs(lam - ref) / ref) < 1e-10
+    assert abs(ref[0] - 0.0181123) < 1e-7 and abs(ref[49] - 0.6349859) < 1e-7
+
+
+def test_c1_closed_form_eigenvectors(c1_solution):
+    p, lam, V, st = c1_solution
+    n = 32
+    x = np.arange(1, n + 1)
+    modes = []
+    for j in range(1, n + 1):
+        for k in range(1, n + 1):
+            s = 4 * np.sin(j * np.pi / 66) ** 2 + 4 * np.sin(k * np.pi / 66) ** 2
+            modes.append((s, j, k))
+    modes.sort()
+    Vref = np.zeros((n * n, 50))
+    for c, (s, j, k) in enumerate(modes[:50]):
+        u = np.outer(np.sin(k * np.pi * x / 33), np.sin(j * np.pi * x / 33)).ravel()
+        Vref[:, c] = u / np.linalg.norm(u)
+    ang, cl = dense.cluster_angles(np.array([m[0] for m in modes[:50]]), Vref, V)
+    assert ang.max() < 1e-8
+    assert len(cl) == 28
+    assert dense.rel_residuals(p.scipy(), lam, V).max() < 1e-9
+
+
+def test_c1_stats_schema(c1_solution):
+    st = c1_solution[3]
+    assert set(st.levels) == {0, 1, 2, 3}
+    assert st.levels[0]["ext_out"] == 50
+
+
+def test_rgg_small_vs_dense_and_components():
+    p = wl.rgg(400, 11, mean_degree=5)
+    A = p.scipy()
+    ncomp = dense.component_count(A)
+    assert ncomp > 1
+    lam, V = krylov.eig_leftmost(A, 30, 1e-11, mmd_kwargs=dict(coords=p.coords, levels=2, targets=(4, 8)))
+    lr, Vr = dense.smallest_dense(A, 30)
+    # the shifted null cluster: multiplicity = number of components, value exactly 1e-6
+    assert np.sum(np.abs(lam - 1e-6) < 1e-12) == ncomp
+    big = lr > 2e-6
+    assert np.max(np.abs(lam[big] - lr[big]) / lr[big]) < 1e-10
+    ang, cl = dense.cluster_angles(lr, Vr, V)
+    assert ang.max() < 1e-8
+
+
+def test_no_hierarchy_is_plain_irlm_and_agrees():
+    p = wl.knn_gmm(300, 10, 1)
+    A = p.scipy()
+    lam0, V0 = krylov.eig_leftmost(A, 15, 1e-11, mmd_kwargs=dict(levels=0))
+    lam2, V2 = krylov.eig_leftmost(A, 15, 1e-11, mmd_kwargs=dict(coords=p.coords, levels=2, targets=(4, 8)))
+    assert np.max(np.abs(lam0 - lam2) / lam0) < 1e-10
+    lr, _ = dense.smallest_dense(A, 15)
+    assert abs(lam0[0] - 1e-6) < 1e-15
+    assert np.max(np.abs(lam0[1:] - lr[1:]) / lr[1:]) < 1e-10
+
+
+def test_grid3d_constant_coefficient_closed_form():
+    m = 8
+    p = wl.grid3d_lognormal(m, 0, sigma=0.0)
+    lam, V = krylov.eig_leftmost(p.scipy(), 20, 1e-11, mmd_kwargs=dict(
+        coords=p.coords, grid=p.grid, levels=1, grid_blocks=(2,), r_hops=1))
+    j = np.arange(1, m + 1)
+    s = 4 * np.sin(j * np.pi / (2 * (m + 1))) ** 2
+    ref = np.sort((s[:, None, None] + s[None, :, None] + s[None, None, :]).ravel())[:20]
+    assert np.max(np.abs(lam - ref) / ref) < 1e-10
