@@ -1,0 +1,178 @@
+/*
+ * mmdeig — leftmost eigenpairs of a sparse SPD matrix by the hierarchically
+ * preconditioned eigensolver of Hou, Huang, Lam and Zhang, "A Fast
+ * Hierarchically Preconditioned Eigensolver Based on Multiresolution Matrix
+ * Decomposition" (arXiv 1804.03415), on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Plain pointers and sizes only.  Every function returns an int
+ * status (MMD_OK = 0); on failure mmd_last_error() returns a thread-local
+ * message describing the cause.  All device work is enqueued on the
+ * caller's HIP stream (void* hip_stream, NULL = the default stream); results
+ * in device buffers are valid once that stream has completed.  Host output
+ * buffers are filled before the call returns.
+ *
+ * Memory ownership: the caller owns every buffer it passes; the library never
+ * frees caller memory and keeps no caller pointer after a call returns.  A
+ * handle owns the device copy of the decomposition and its workspaces until
+ * mmd_free().  Calls that use the same handle must not overlap.
+ */
+#ifndef MMDEIG_H
+#define MMDEIG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+#define MMD_OK 0
+#define MMD_EINVAL 1        /* bad argument: non-square, unsorted or asymmetric
+                               pattern, NaN, nev out of range, bad level/op    */
+#define MMD_ENOTSPD 2       /* nonpositive diagonal or CG curvature p^T A p <= 0 */
+#define MMD_EUNSUPPORTED 3  /* positive off-diagonal / negative self-loop: no
+                               edge-type energy decomposition (Section 2.1)    */
+#define MMD_ENOCONV 4       /* iteration cap reached; partial results          */
+#define MMD_ENOMEM 5        /* device or host allocation failed                */
+#define MMD_EHIP 6          /* a HIP runtime call failed                       */
+
+/* ------------------------------------------------------------------ inputs */
+/* Symmetric sparse matrix in CSR form.  rowptr has n+1 entries (int64),
+ * colind nnz sorted column indices per row (int32), val nnz float64 values.
+ * mem = 0: the three arrays are host memory; mem = 1: device memory.
+ * Optional geometry steers the partitioner: coords (host, n x coord_dim
+ * row-major float64, may be NULL) for graphs; grid_dim = 2 or 3 with
+ * grid[0..grid_dim-1] = (nx, ny[, nz]) for tensor grids whose vertex
+ * (x, y, z) has index (z*ny + y)*nx + x (grid_dim = 0: not a grid). */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int64_t* rowptr;
+  const int32_t* colind;
+  const double* val;
+  int32_t mem;
+  int32_t coord_dim;
+  const double* coords;
+  int32_t grid_dim;
+  int32_t grid[3];
+} mmd_csr;
+
+/* Decomposition options (Sections 2.2-2.3).  Zero-initialised fields take the
+ * defaults given in brackets. */
+typedef struct {
+  int32_t levels;          /* number of coarse levels K [3]                      */
+  int32_t n_targets;       /* entries used in targets[] [2: {4, 8}]              */
+  int32_t targets[8];      /* greedy patch size of level k (last entry repeats)  */
+  int32_t n_grid_blocks;   /* entries used in grid_blocks[] [2: {4, 2}]          */
+  int32_t grid_blocks[8];  /* tensor block edge of level k for grids             */
+  int32_t r_hops;          /* localisation radius of Psi in patch hops [1]       */
+  int64_t exact_max_n;     /* levels whose fine size <= this use the exact Psi [0] */
+  int32_t min_coarse;      /* stop coarsening below this many dofs [4]           */
+} mmd_build_opts;
+
+/* Solver options (Section 5 parameter choice).  Zero fields take defaults. */
+typedef struct {
+  double alpha;            /* mu_re^(k) = alpha eps_{k+1} [3]                    */
+  double beta;             /* mu_ex^(k) = beta eps_k [1]                         */
+  int32_t restart_mult;    /* c: shifts per restart = c d [1]                    */
+  int32_t reserved;
+  uint64_t seed;           /* Philox key of the random start vectors [0]         */
+  int32_t max_restarts;    /* per extension [2000]                               */
+  int32_t max_refine;      /* refinement iterations per level [200]              */
+} eig_opts;
+
+#define MMD_MAX_LEVELS 16
+/* Per-level counters in the paper's statistics schema (Section 7.3). */
+typedef struct {
+  int32_t K;
+  int32_t nconv;
+  int64_t ref_in[MMD_MAX_LEVELS], ref_out[MMD_MAX_LEVELS], ref_iter[MMD_MAX_LEVELS];
+  int64_t cg_B_calls[MMD_MAX_LEVELS], cg_B_iters[MMD_MAX_LEVELS];
+  int64_t pcg_A_calls[MMD_MAX_LEVELS], pcg_A_iters[MMD_MAX_LEVELS];
+  int64_t cg_M_iters[MMD_MAX_LEVELS];
+  int64_t ext_in[MMD_MAX_LEVELS], ext_out[MMD_MAX_LEVELS];
+  int64_t lanczos_steps[MMD_MAX_LEVELS], restarts[MMD_MAX_LEVELS];
+  int64_t missed_swaps;
+  double seconds_level[MMD_MAX_LEVELS];
+  double seconds_total;
+} eig_stats;
+
+typedef struct mmd_handle mmd_handle;
+
+/* Build the K-level multiresolution decomposition of A (Section 2.3, eq. MMD):
+ * per level the patch partition, the local basis phi_j (smallest eigenvector
+ * of the patch energy, q = 1, Section 2.2), one Householder reflector per
+ * patch (the complement U, Lemma 2.3), the localised Psi (eq. psi_closedform
+ * in its constrained-energy form, Appendix A) and A^(k) = Psi^T A^(k-1) Psi,
+ * M^(k) = Psi^T M^(k-1) Psi.  Runs on the host, uploads the level operators
+ * on hip_stream.  Errors: MMD_EINVAL, MMD_EUNSUPPORTED, MMD_ENOTSPD,
+ * MMD_ENOMEM, MMD_EHIP.  *out is set only on success. */
+int mmd_build(const mmd_csr* A, const mmd_build_opts* opts, void* hip_stream,
+              mmd_handle** out);
+
+/* Level sizes and error factors: K, N^(k) for k = 0..K (sizes[K+1]),
+ * nnz(A^(k)) and nnz(M^(k)) (nnzA/nnzM[K+1], level 0: nnz(A), 0) and the
+ * cumulative compression errors eps_k (eps[K+1], eps_0 = 0; Theorem 2.6).
+ * Any output pointer may be NULL.  The arrays must hold MMD_MAX_LEVELS. */
+int mmd_info(const mmd_handle* h, int32_t* K, int64_t* sizes, int64_t* nnzA,
+             int64_t* nnzM, double* eps);
+
+/* Copy one level object to host CSR buffers (for inspection and tests).
+ * which: 0 = A^(k), 1 = M^(k) (k >= 1), 2 = Psi^(k) (k >= 1, N^(k-1) x N^(k)).
+ * Pass rowptr = NULL to query n_rows / nnz only. */
+int mmd_export(const mmd_handle* h, int32_t level, int32_t which, int64_t* n_rows,
+               int64_t* n_cols, int64_t* nnz, int64_t* rowptr, int32_t* colind,
+               double* val);
+
+/* The nev smallest eigenpairs of A (Alg. 6, continued to level 0 with
+ * A^(0) = A, M^(0) = I): coarsest-level generalised eigenproblem, then per
+ * level reform (V <- Psi V), Eigenpair Refinement (Alg. 5) and Eigenpair
+ * Extension (Alg. 4, operator OP = PCG with preconditioner M^(k), Section
+ * 4), followed by a multiplicity check and an inverse-iteration +
+ * Rayleigh-Ritz output step on level 0.
+ *   tol    relative accuracy on level 0 (CG tolerance, Ritz residual
+ *          relative to the Ritz value); coarse levels use 0.1 eps_k.
+ *   evals  host float64 [nev], ascending.
+ *   evecs  device float64, column-major n x nev (eigenvector i at
+ *          evecs + i*n), unit 2-norm, largest-magnitude entry positive.
+ *   st     optional counters.
+ * Errors: MMD_EINVAL (nev out of range), MMD_ENOTSPD, MMD_ENOCONV, MMD_EHIP. */
+int eig_leftmost(mmd_handle* h, int32_t nev, double tol, const eig_opts* opts,
+                 double* evals, double* evecs, eig_stats* st, void* hip_stream);
+
+/* Apply one level operator to a block of b columns (device, row-major with
+ * leading dimension b).  op: 0 = A^(k) (N^(k) -> N^(k)), 1 = M^(k),
+ * 2 = B^(k+1) = U^T A^(k) U (reduced -> reduced, needs k < K),
+ * 3 = U^(k+1) (reduced -> N^(k)), 4 = U^(k+1)^T (N^(k) -> reduced),
+ * 5 = Psi^(k+1) (N^(k+1) -> N^(k)).  Level 0 A is applied in edge form
+ * y_i = s_i x_i + sum_j w_ij (x_i - x_j) (Section 2.1 elements). */
+int mmd_apply(mmd_handle* h, int32_t level, int32_t op, const double* X, double* Y,
+              int32_t b, void* hip_stream);
+
+/* Column-wise solves on one level, b independent right-hand sides (device,
+ * row-major, leading dimension b).  kind 0: pcg(A^(k), rhs, M^(k), x0, tol)
+ * of Section 4 (flexible PCG with an inner CG on M^(k) to 0.1 tol; plain CG on
+ * level 0); kind 1: cg(B^(k+1), rhs, -, x0, tol) (Alg. 5 start block).  X holds
+ * x0 on entry (use_x0 != 0) and the solution on exit.  iters (host int32[b],
+ * may be NULL) receives the outer iteration counts. */
+int mmd_solve(mmd_handle* h, int32_t level, int32_t kind, const double* rhs, double* X,
+              int32_t b, int32_t use_x0, double tol, int32_t* iters, void* hip_stream);
+
+/* Y = A X for a caller-supplied device CSR (int64 rowptr, int32 colind,
+ * float64 val; n_rows x n_cols) and a row-major block X [n_cols x b] ->
+ * Y [n_rows x b] (CSR sparse-matrix times dense block, Section 7.3 "Main
+ * Cost" unit). */
+int mmdk_spmm(int64_t n_rows, int64_t n_cols, const int64_t* rowptr, const int32_t* colind,
+              const double* val, const double* X, double* Y, int32_t b, void* hip_stream);
+
+/* Release a handle and everything it owns (NULL is ignored). */
+void mmd_free(mmd_handle* h);
+
+/* Thread-local message for the last nonzero status on this thread. */
+const char* mmd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MMDEIG_H */

@@ -1,0 +1,151 @@
+"""Python face of the C ABI: decomposition handles and the eigensolver calls.
+
+Device buffers are torch tensors on the current HIP device; all work is
+enqueued on the current torch stream.  Functions mirror include/mmdeig.h.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import MMDError, check, eig_opts, eig_stats, lib, mmd_build_opts, mmd_csr
+
+OPS = {"A": 0, "M": 1, "B": 2, "U": 3, "Ut": 4, "Psi": 5}
+
+
+def build_options(levels=3, targets=(4, 8), grid_blocks=(4, 2), r_hops=1, exact_max_n=0,
+                  min_coarse=4):
+    o = mmd_build_opts()
+    o.levels = levels if levels > 0 else -1
+    o.n_targets = len(targets)
+    for i, t in enumerate(targets):
+        o.targets[i] = t
+    o.n_grid_blocks = len(grid_blocks)
+    for i, t in enumerate(grid_blocks):
+        o.grid_blocks[i] = t
+    o.r_hops = r_hops
+    o.exact_max_n = exact_max_n
+    o.min_coarse = min_coarse
+    return o
+
+
+def solver_options(alpha=3.0, beta=1.0, restart_mult=1, seed=0, max_restarts=2000,
+                   max_refine=200):
+    o = eig_opts()
+    o.alpha, o.beta, o.restart_mult, o.seed = alpha, beta, restart_mult, seed
+    o.max_restarts, o.max_refine = max_restarts, max_refine
+    return o
+
+
+class Decomposition:
+    """Handle of a multiresolution decomposition (mmd_build ... mmd_free)."""
+
+    def __init__(self, rowptr, col, val, coords=None, grid=None, stream=None, **opts):
+        rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        n = rowptr.size - 1
+        c = mmd_csr()
+        c.n, c.nnz = n, int(rowptr[-1])
+        c.rowptr, c.colind, c.val = _lib._ptr(rowptr), _lib._ptr(col), _lib._ptr(val)
+        c.mem = 0
+        self._coords = None
+        if coords is not None:
+            self._coords = np.ascontiguousarray(coords, dtype=np.float64)
+            c.coord_dim = self._coords.shape[1]
+            c.coords = _lib._ptr(self._coords)
+        if grid is not None:
+            c.grid_dim = len(grid)
+            for i, g in enumerate(grid):
+                c.grid[i] = int(g)
+        o = build_options(**opts)
+        h = ctypes.c_void_p()
+        check(lib().mmd_build(ctypes.byref(c), ctypes.byref(o), _lib._stream(stream), ctypes.byref(h)))
+        self.h = h
+        self.n = n
+
+    @classmethod
+    def from_problem(cls, p, **opts):
+        return cls(p.rowptr, p.col, p.val, coords=None if p.grid else p.coords, grid=p.grid, **opts)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib().mmd_free(h)
+            self.h = None
+
+    def info(self):
+        K = ctypes.c_int32()
+        sizes = np.zeros(_lib.MMD_MAX_LEVELS, np.int64)
+        nnzA = np.zeros_like(sizes)
+        nnzM = np.zeros_like(sizes)
+        eps = np.zeros(_lib.MMD_MAX_LEVELS)
+        check(lib().mmd_info(self.h, ctypes.byref(K), _lib._ptr(sizes), _lib._ptr(nnzA),
+                             _lib._ptr(nnzM), _lib._ptr(eps)))
+        k = K.value
+        return {"K": k, "sizes": sizes[:k + 1].tolist(), "nnzA": nnzA[:k + 1].tolist(),
+                "nnzM": nnzM[:k + 1].tolist(), "eps": eps[:k + 1].tolist()}
+
+    def export(self, level, which):
+        """Host CSR (rowptr, col, val, shape) of A^(k) (0), M^(k) (1) or Psi^(k) (2)."""
+        nr, nc, nz = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        check(lib().mmd_export(self.h, level, which, ctypes.byref(nr), ctypes.byref(nc),
+                               ctypes.byref(nz), None, None, None))
+        rp = np.zeros(nr.value + 1, np.int64)
+        ci = np.zeros(nz.value, np.int32)
+        v = np.zeros(nz.value)
+        check(lib().mmd_export(self.h, level, which, None, None, None, _lib._ptr(rp),
+                               _lib._ptr(ci), _lib._ptr(v)))
+        return rp, ci, v, (nr.value, nc.value)
+
+    def apply(self, level, op, X, stream=None):
+        """Y = op X for a row-major [rows, b] float64 CUDA tensor X (returns a new tensor)."""
+        import torch
+        X = X.contiguous()
+        b = X.shape[1] if X.dim() == 2 else 1
+        out_rows = self._out_rows(level, OPS[op])
+        Y = torch.empty((out_rows, b), dtype=torch.float64, device=X.device)
+        check(lib().mmd_apply(self.h, level, OPS[op], _lib._ptr(X), _lib._ptr(Y), b,
+                              _lib._stream(stream)))
+        return Y
+
+    def _out_rows(self, level, op):
+        s = self.info()["sizes"]
+        if op in (0, 1, 3, 5):
+            return s[level]
+        return s[level] - s[level + 1]  # B and U^T map into the reduced space
+
+    def solve(self, level, kind, rhs, x0=None, tol=1e-10, stream=None):
+        """Column-wise PCG on A^(k) (kind 0) or CG on B^(k+1) (kind 1); returns (X, iters)."""
+        import torch
+        rhs = rhs.contiguous()
+        b = rhs.shape[1]
+        X = torch.zeros_like(rhs) if x0 is None else x0.clone().contiguous()
+        it = np.zeros(b, np.int32)
+        check(lib().mmd_solve(self.h, level, kind, _lib._ptr(rhs), _lib._ptr(X), b,
+                              0 if x0 is None else 1, tol, _lib._ptr(it), _lib._stream(stream)))
+        return X, it
+
+    def eig_leftmost(self, nev, tol=1e-10, stream=None, **opts):
+        """(evals ascending numpy [nev], evecs CUDA tensor [nev, n], stats dict)."""
+        import torch
+        evals = np.zeros(nev)
+        evecs = torch.empty((nev, self.n), dtype=torch.float64, device="cuda")
+        st = eig_stats()
+        o = solver_options(**opts)
+        check(lib().eig_leftmost(self.h, nev, tol, ctypes.byref(o), _lib._ptr(evals),
+                                 _lib._ptr(evecs), ctypes.byref(st), _lib._stream(stream)))
+        return evals, evecs, st.as_dict()
+
+
+def spmm(rowptr, col, val, X, n_cols=None, stream=None):
+    """Y = A X for a CUDA CSR (int64 rowptr, int32 col, float64 val) and row-major X."""
+    import torch
+    n_rows = rowptr.numel() - 1
+    n_cols = X.shape[0] if n_cols is None else n_cols
+    X = X.contiguous()
+    b = X.shape[1]
+    Y = torch.empty((n_rows, b), dtype=torch.float64, device=X.device)
+    check(lib().mmdk_spmm(n_rows, n_cols, _lib._ptr(rowptr), _lib._ptr(col), _lib._ptr(val),
+                          _lib._ptr(X), _lib._ptr(Y), b, _lib._stream(stream)))
+    return Y

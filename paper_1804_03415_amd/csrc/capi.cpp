@@ -1,0 +1,162 @@
+// C-ABI entry points (declared in include/mmdeig.h).  Each call converts
+// exceptions into a status code and a thread-local message.
+#include <cstring>
+#include <string>
+
+#include "handle.h"
+#include "solver.h"
+
+namespace mmd {
+namespace {
+thread_local std::string g_last_error;
+}
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+const char* g_last_error_cstr() { return g_last_error.c_str(); }
+}  // namespace mmd
+
+namespace {
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    f();
+    return MMD_OK;
+  } catch (const mmd::Error& e) {
+    mmd::set_last_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    mmd::set_last_error("host allocation failed");
+    return MMD_ENOMEM;
+  } catch (const std::exception& e) {
+    mmd::set_last_error(e.what());
+    return MMD_EINVAL;
+  }
+}
+
+eig_opts default_opts(const eig_opts* o) {
+  eig_opts d;
+  std::memset(&d, 0, sizeof(d));
+  if (o) d = *o;
+  return d;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mmd_build(const mmd_csr* A, const mmd_build_opts* opts, void* hip_stream, mmd_handle** out) {
+  return guarded([&] {
+    MMD_REQUIRE(A && out, MMD_EINVAL, "null argument");
+    MMD_REQUIRE(A->rowptr && A->colind && A->val, MMD_EINVAL, "null CSR array");
+    mmd_build_opts o;
+    std::memset(&o, 0, sizeof(o));
+    if (opts) o = *opts;
+    auto* h = new mmd_handle();
+    try {
+      mmd::build_hierarchy(*h, *A, o);
+      mmd::upload_hierarchy(*h, static_cast<hipStream_t>(hip_stream));
+    } catch (...) {
+      delete h;
+      throw;
+    }
+    *out = h;
+  });
+}
+
+int mmd_info(const mmd_handle* h, int32_t* K, int64_t* sizes, int64_t* nnzA, int64_t* nnzM,
+             double* eps) {
+  return guarded([&] {
+    MMD_REQUIRE(h, MMD_EINVAL, "null handle");
+    if (K) *K = h->K;
+    for (int k = 0; k <= h->K; ++k) {
+      if (sizes) sizes[k] = h->host[k].n;
+      if (nnzA) nnzA[k] = h->host[k].A.nnz();
+      if (nnzM) nnzM[k] = k == 0 ? 0 : h->host[k].M.nnz();
+      if (eps) eps[k] = h->eps[k];
+    }
+  });
+}
+
+int mmd_export(const mmd_handle* h, int32_t level, int32_t which, int64_t* n_rows,
+               int64_t* n_cols, int64_t* nnz, int64_t* rowptr, int32_t* colind, double* val) {
+  return guarded([&] {
+    MMD_REQUIRE(h, MMD_EINVAL, "null handle");
+    MMD_REQUIRE(level >= 0 && level <= h->K, MMD_EINVAL, "level out of range");
+    MMD_REQUIRE(which >= 0 && which <= 2, MMD_EINVAL, "which must be 0, 1 or 2");
+    MMD_REQUIRE(which == 0 || level >= 1, MMD_EINVAL, "M and Psi exist for levels >= 1");
+    const mmd::LevelHost& L = h->host[level];
+    const mmd::HostCSR& X = which == 0 ? L.A : (which == 1 ? L.M : L.Psi);
+    if (n_rows) *n_rows = X.n_rows;
+    if (n_cols) *n_cols = X.n_cols;
+    if (nnz) *nnz = X.nnz();
+    if (rowptr) {
+      MMD_REQUIRE(colind && val, MMD_EINVAL, "null output array");
+      std::copy(X.ptr.begin(), X.ptr.end(), rowptr);
+      std::copy(X.col.begin(), X.col.end(), colind);
+      std::copy(X.val.begin(), X.val.end(), val);
+    }
+  });
+}
+
+int eig_leftmost(mmd_handle* h, int32_t nev, double tol, const eig_opts* opts, double* evals,
+                 double* evecs, eig_stats* st, void* hip_stream) {
+  return guarded([&] {
+    MMD_REQUIRE(h && evals && evecs, MMD_EINVAL, "null argument");
+    mmd::Solver sv(*h, static_cast<hipStream_t>(hip_stream), default_opts(opts), st);
+    sv.leftmost(nev, tol, evals, evecs);
+  });
+}
+
+int mmd_apply(mmd_handle* h, int32_t level, int32_t op, const double* X, double* Y, int32_t b,
+              void* hip_stream) {
+  return guarded([&] {
+    MMD_REQUIRE(h && X && Y, MMD_EINVAL, "null argument");
+    mmd::Solver sv(*h, static_cast<hipStream_t>(hip_stream), default_opts(nullptr), nullptr);
+    sv.apply_op(level, op, X, Y, b);
+    MMD_HIP(hipStreamSynchronize(static_cast<hipStream_t>(hip_stream)));
+  });
+}
+
+int mmd_solve(mmd_handle* h, int32_t level, int32_t kind, const double* rhs, double* X,
+              int32_t b, int32_t use_x0, double tol, int32_t* iters, void* hip_stream) {
+  return guarded([&] {
+    MMD_REQUIRE(h && rhs && X, MMD_EINVAL, "null argument");
+    mmd::Solver sv(*h, static_cast<hipStream_t>(hip_stream), default_opts(nullptr), nullptr);
+    sv.solve(level, kind, rhs, X, b, use_x0 != 0, tol, iters);
+  });
+}
+
+int mmdk_spmm(int64_t n_rows, int64_t n_cols, const int64_t* rowptr, const int32_t* colind,
+              const double* val, const double* X, double* Y, int32_t b, void* hip_stream) {
+  return guarded([&] {
+    MMD_REQUIRE(n_rows >= 0 && n_rows < (int64_t(1) << 31) && n_cols >= 0 &&
+                    n_cols < (int64_t(1) << 31),
+                MMD_EINVAL, "dimension out of range");
+    MMD_REQUIRE(b > 0, MMD_EINVAL, "b must be positive");
+    if (n_rows == 0) return;
+    MMD_REQUIRE(rowptr && X && Y, MMD_EINVAL, "null argument");
+    const auto s = static_cast<hipStream_t>(hip_stream);
+    int64_t nnz = 0;
+    MMD_HIP(hipMemcpyAsync(&nnz, rowptr + n_rows, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    MMD_HIP(hipStreamSynchronize(s));
+    MMD_REQUIRE(nnz >= 0 && nnz < (int64_t(1) << 31), MMD_EINVAL, "nnz out of range");
+    mmd::DBuf<int> ptr32(n_rows + 1);
+    mmd::i64_to_i32(rowptr, ptr32.p, n_rows + 1, s);
+    mmd::CsrView A;
+    A.n_rows = static_cast<int>(n_rows);
+    A.n_cols = static_cast<int>(n_cols);
+    A.nnz = nnz;
+    A.rowptr = ptr32.p;
+    A.col = colind;
+    A.val = val;
+    A.avg_row = n_rows ? static_cast<double>(nnz) / n_rows : 1.0;
+    mmd::spmm(A, X, b, Y, b, b, s);
+    MMD_HIP(hipStreamSynchronize(s));
+  });
+}
+
+void mmd_free(mmd_handle* h) { delete h; }
+
+const char* mmd_last_error(void) { return mmd::g_last_error_cstr(); }
+
+}  // extern "C"

@@ -1,0 +1,866 @@
+// Device kernels of the hierarchical eigensolver for CDNA4 (gfx950, wave64).
+//
+// Hot path (Section 4, operator OP, and Alg. 5): CSR SpMM with A^(k), M^(k)
+// and Psi, the patch Householder transforms that realise U and U^T, the
+// vector updates and column dot products of CG / flexible PCG, and the
+// tall-skinny FP64 products of the Lanczos re-orthogonalisation and the
+// Rayleigh-Ritz steps.  Blocks of vectors are row-major (N x b, leading
+// dimension ld) so one gathered row of X serves all b right-hand sides with
+// one coalesced load.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace mmd {
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+
+inline int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
+
+inline void check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error(MMD_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------------ SpMM
+// One wavefront handles R = 64 / (LPR * CT) rows and a tile of CT columns;
+// lane = (r, s, c): c = lane % CT, s = (lane / CT) % LPR, r = lane / (CT*LPR).
+// The LPR lanes of a (row, column) pair stride over the row's nonzeros and are
+// combined with xor shuffles.  Rows are visited in a grid-stride loop so each
+// block can keep per-column partial dot products for the fused CG epilogue.
+template <int LPR, int CT, bool EDGE, bool FUSE, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_spmm(
+    int n_rows, const int* __restrict__ rowptr, const int* __restrict__ col,
+    const double* __restrict__ val, const double* __restrict__ diag,
+    const double* __restrict__ X, int ldx, double* __restrict__ Y, int ldy, int b,
+    int first, const double* __restrict__ beta, double* __restrict__ P, int ldp,
+    double* __restrict__ partial, const double* __restrict__ dotw, int lddot) {
+  constexpr int R = kWave / (LPR * CT);
+  constexpr int WPB = kBlock / kWave;
+  __shared__ double red[WPB * R * CT];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int c = lane % CT;
+  const int s = (lane / CT) % LPR;
+  const int r = lane / (CT * LPR);
+  const int c0 = blockIdx.y * CT;
+  const int colx = c0 + c;
+  const bool cok = colx < b;
+  const double bt = (FUSE && cok && !first) ? beta[colx] : 0.0;
+  double dsum = 0.0;
+  const int groups = (n_rows + R - 1) / R;
+  for (int g = blockIdx.x * WPB + wid; g < groups; g += gridDim.x * WPB) {
+    const int row = g * R + r;
+    double acc = 0.0;
+    double xi = 0.0;
+    if (row < n_rows && cok) {
+      const int lo = rowptr[row], hi = rowptr[row + 1];
+      if (EDGE) xi = X[(size_t)row * ldx + colx];
+      for (int k = lo + s; k < hi; k += LPR) {
+        const double xj = X[(size_t)col[k] * ldx + colx];
+        if (EDGE)
+          acc += val[k] * (xi - xj);
+        else
+          acc += val[k] * xj;
+      }
+    }
+#pragma unroll
+    for (int off = CT; off < CT * LPR; off <<= 1) acc += __shfl_xor(acc, off, kWave);
+    if (s == 0 && row < n_rows && cok) {
+      double y = EDGE ? diag[row] * xi + acc : acc;
+      if (FUSE) {
+        const size_t iy = (size_t)row * ldy + colx;
+        const size_t ip = (size_t)row * ldp + colx;
+        double pn;
+        if (first) {
+          pn = X[(size_t)row * ldx + colx];
+        } else {
+          y += bt * Y[iy];
+          pn = X[(size_t)row * ldx + colx] + bt * P[ip];
+        }
+        P[ip] = pn;
+        dsum += pn * y;
+      } else if (DOT) {
+        dsum += dotw[(size_t)row * lddot + colx] * y;
+      }
+      Y[(size_t)row * ldy + colx] = y;
+    }
+  }
+  if (FUSE || DOT) {
+    // lanes with s == 0 hold (r, c) partial sums; combine over r and waves
+    if (s == 0) red[(wid * R + r) * CT + c] = dsum;
+    __syncthreads();
+    if (threadIdx.x < CT) {
+      double t = 0.0;
+      for (int q = 0; q < WPB * R; ++q) t += red[q * CT + threadIdx.x];
+      const int cc = c0 + threadIdx.x;
+      if (cc < b) partial[(size_t)blockIdx.x * b + cc] = t;
+    }
+  }
+}
+
+template <int LPR, int CT>
+int launch_spmm_t(const CsrView& A, const double* X, int ldx, double* Y, int ldy, int b,
+                  hipStream_t s, bool fuse, bool first, const double* beta, double* P, int ldp,
+                  double* partial, const double* dotw, int lddot) {
+  constexpr int R = kWave / (LPR * CT);
+  constexpr int WPB = kBlock / kWave;
+  const int groups = ceil_div(A.n_rows, R);
+  int gx = ceil_div(groups, WPB);
+  const bool red = fuse || dotw != nullptr;
+  if (red) gx = std::min(gx, kRedBlocks);
+  gx = std::max(gx, 1);
+  dim3 grid(gx, ceil_div(b, CT));
+  const bool edge = A.diag != nullptr;
+#define MMD_SPMM_CASE(E, F, D)                                                             \
+  hipLaunchKernelGGL((k_spmm<LPR, CT, E, F, D>), grid, dim3(kBlock), 0, s, A.n_rows,       \
+                     A.rowptr, A.col, A.val, A.diag, X, ldx, Y, ldy, b, first ? 1 : 0, beta, \
+                     P, ldp, partial, dotw, lddot)
+  if (edge) {
+    if (fuse) MMD_SPMM_CASE(true, true, false);
+    else if (dotw) MMD_SPMM_CASE(true, false, true);
+    else MMD_SPMM_CASE(true, false, false);
+  } else {
+    if (fuse) MMD_SPMM_CASE(false, true, false);
+    else if (dotw) MMD_SPMM_CASE(false, false, true);
+    else MMD_SPMM_CASE(false, false, false);
+  }
+#undef MMD_SPMM_CASE
+  check_launch();
+  return gx;
+}
+
+// ------------------------------------------------------------------ Householder
+__global__ void k_house_ut(int npatch, const int* __restrict__ ptr, const int* __restrict__ mem,
+                           const double* __restrict__ u, const double* __restrict__ scale,
+                           const double* __restrict__ x, int ldx, double* __restrict__ y,
+                           int ldy, int b) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)npatch * b) return;
+  const int j = static_cast<int>(t / b);
+  const int c = static_cast<int>(t % b);
+  const int lo = ptr[j], hi = ptr[j + 1];
+  double d = 0.0;
+  for (int q = lo; q < hi; ++q) d += u[q] * x[(size_t)mem[q] * ldx + c];
+  const double sc = scale[j] * d;
+  const int base = lo - j - 1;  // reduced index of slot q is base + (q - lo)
+  for (int q = lo + 1; q < hi; ++q)
+    y[(size_t)(base + (q - lo)) * ldy + c] = x[(size_t)mem[q] * ldx + c] - sc * u[q];
+}
+
+__global__ void k_house_u(int npatch, const int* __restrict__ ptr, const int* __restrict__ mem,
+                          const double* __restrict__ u, const double* __restrict__ scale,
+                          const double* __restrict__ y, int ldy, double* __restrict__ x,
+                          int ldx, int b) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)npatch * b) return;
+  const int j = static_cast<int>(t / b);
+  const int c = static_cast<int>(t % b);
+  const int lo = ptr[j], hi = ptr[j + 1];
+  const int base = lo - j - 1;
+  double d = 0.0;
+  for (int q = lo + 1; q < hi; ++q) d += u[q] * y[(size_t)(base + (q - lo)) * ldy + c];
+  const double sc = scale[j] * d;
+  x[(size_t)mem[lo] * ldx + c] = -sc * u[lo];
+  for (int q = lo + 1; q < hi; ++q)
+    x[(size_t)mem[q] * ldx + c] = y[(size_t)(base + (q - lo)) * ldy + c] - sc * u[q];
+}
+
+// ------------------------------------------------------------------ column reductions
+// Thread layout shared by the reduction kernels: for b <= 256 a block uses
+// tb = (256 / b) * b threads, thread t owns column t % b and row offset t / b;
+// for b > 256 the block walks column tiles of 256 with one row per step.
+struct ColMap {
+  int b, tb, rstep, col, roff;
+  bool act;
+};
+
+__device__ inline ColMap colmap(int b, int tile_c0) {
+  ColMap m;
+  m.b = b;
+  if (b <= kBlock) {
+    m.tb = (kBlock / b) * b;
+    m.rstep = kBlock / b;
+    m.col = threadIdx.x % b;
+    m.roff = threadIdx.x / b;
+    m.act = threadIdx.x < m.tb;
+  } else {
+    m.tb = kBlock;
+    m.rstep = 1;
+    m.col = tile_c0 + threadIdx.x;
+    m.roff = 0;
+    m.act = m.col < b;
+  }
+  return m;
+}
+
+__device__ inline void block_col_store(double v, const ColMap& m, double* partial) {
+  __shared__ double sh[kBlock];
+  sh[threadIdx.x] = m.act ? v : 0.0;
+  __syncthreads();
+  if (m.b <= kBlock) {
+    if (threadIdx.x < m.b) {
+      double t = 0.0;
+      for (int q = threadIdx.x; q < m.tb; q += m.b) t += sh[q];
+      partial[(size_t)blockIdx.x * m.b + threadIdx.x] = t;
+    }
+  } else if (m.act) {
+    partial[(size_t)blockIdx.x * m.b + m.col] = sh[threadIdx.x];
+  }
+  __syncthreads();
+}
+
+template <int MODE>  // 0: X.*Y ; 1: two dots X.*Y1, X.*Y2
+__global__ __launch_bounds__(kBlock) void k_coldot(const double* __restrict__ X, int ldx,
+                                                   const double* __restrict__ Y1,
+                                                   const double* __restrict__ Y2, int ldy,
+                                                   int n, int b, double* __restrict__ p1,
+                                                   double* __restrict__ p2) {
+  const int ntile = b <= kBlock ? 1 : (b + kBlock - 1) / kBlock;
+  for (int tile = 0; tile < ntile; ++tile) {
+    ColMap m = colmap(b, tile * kBlock);
+    double a1 = 0.0, a2 = 0.0;
+    if (m.act) {
+      for (int i = blockIdx.x * m.rstep + m.roff; i < n; i += gridDim.x * m.rstep) {
+        const double x = X[(size_t)i * ldx + m.col];
+        a1 += x * Y1[(size_t)i * ldy + m.col];
+        if (MODE == 1) a2 += x * Y2[(size_t)i * ldy + m.col];
+      }
+    }
+    block_col_store(a1, m, p1);
+    if (MODE == 1) block_col_store(a2, m, p2);
+  }
+}
+
+__global__ void k_reduce_partials(const double* __restrict__ partial, int nblk, int b,
+                                  double* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= b) return;
+  double t = 0.0;
+  for (int q = 0; q < nblk; ++q) t += partial[(size_t)q * b + c];
+  out[c] = t;
+}
+
+__device__ inline double sum_part(const double* __restrict__ p, int nblk, int b, int c) {
+  double t = 0.0;
+  for (int q = 0; q < nblk; ++q) t += p[(size_t)q * b + c];
+  return t;
+}
+
+// ------------------------------------------------------------------ CG scalars
+__global__ void k_cg_init(ColScalars sc, const double* __restrict__ pbn,
+                          const double* __restrict__ prr, int nblk, int b, double tol,
+                          const int* __restrict__ parent) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= b) return;
+  const double bn2 = sum_part(pbn, nblk, b, c);
+  const double rr = prr ? sum_part(prr, nblk, b, c) : bn2;
+  sc.bn2[c] = bn2;
+  sc.rr2[c] = rr;
+  sc.rr[c] = rr;
+  sc.tol2[c] = tol * tol;
+  sc.alpha[c] = 0.0;
+  sc.beta[c] = 0.0;
+  sc.iters[c] = 0;
+  const bool par = parent ? parent[c] != 0 : true;
+  sc.active[c] = (par && bn2 > 0.0 && rr > tol * tol * bn2) ? 1 : 0;
+}
+
+__global__ void k_cg_alpha(ColScalars sc, const double* __restrict__ ppq, int nblk, int b) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= b) return;
+  if (!sc.active[c]) {
+    sc.alpha[c] = 0.0;
+    return;
+  }
+  const double pq = sum_part(ppq, nblk, b, c);
+  if (!(pq > 0.0)) {
+    sc.notspd[0] = 1;
+    sc.active[c] = 0;
+    sc.alpha[c] = 0.0;
+    return;
+  }
+  sc.alpha[c] = sc.rr[c] / pq;
+}
+
+__global__ void k_cg_beta(ColScalars sc, const double* __restrict__ prr, int nblk, int b) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= b) return;
+  if (!sc.active[c]) {
+    sc.beta[c] = 0.0;
+    return;
+  }
+  const double rn = sum_part(prr, nblk, b, c);
+  sc.iters[c] += 1;
+  sc.rr2[c] = rn;
+  if (rn <= sc.tol2[c] * sc.bn2[c]) {
+    sc.active[c] = 0;
+    sc.beta[c] = 0.0;
+    return;
+  }
+  sc.beta[c] = rn / sc.rr[c];
+  sc.rr[c] = rn;
+}
+
+__global__ void k_pcg_conv(ColScalars sc, const double* __restrict__ prr, int nblk, int b) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= b) return;
+  if (!sc.active[c]) return;
+  const double rn = sum_part(prr, nblk, b, c);
+  sc.iters[c] += 1;
+  sc.rr2[c] = rn;
+  if (rn <= sc.tol2[c] * sc.bn2[c]) {
+    sc.active[c] = 0;
+    sc.beta[c] = 0.0;
+  }
+}
+
+__global__ void k_pcg_beta(ColScalars sc, const double* __restrict__ prz,
+                           const double* __restrict__ przo, int nblk, int b) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= b) return;
+  if (!sc.active[c]) {
+    sc.beta[c] = 0.0;
+    return;
+  }
+  const double rz = sum_part(prz, nblk, b, c);
+  const double rzo = sum_part(przo, nblk, b, c);
+  sc.beta[c] = (rz - rzo) / sc.rr[c];
+  sc.rr[c] = rz;
+}
+
+// ------------------------------------------------------------------ elementwise
+__global__ __launch_bounds__(kBlock) void k_cg_update(double* __restrict__ X, int ldx,
+                                                      double* __restrict__ R,
+                                                      const double* __restrict__ P,
+                                                      const double* __restrict__ Q, int ld,
+                                                      int n, int b,
+                                                      const double* __restrict__ alpha,
+                                                      double* __restrict__ partial) {
+  const int ntile = b <= kBlock ? 1 : (b + kBlock - 1) / kBlock;
+  for (int tile = 0; tile < ntile; ++tile) {
+    ColMap m = colmap(b, tile * kBlock);
+    double acc = 0.0;
+    if (m.act) {
+      const double a = alpha[m.col];
+      for (int i = blockIdx.x * m.rstep + m.roff; i < n; i += gridDim.x * m.rstep) {
+        const size_t idx = (size_t)i * ld + m.col;
+        double r = R[idx];
+        if (a != 0.0) {
+          X[(size_t)i * ldx + m.col] += a * P[idx];
+          r -= a * Q[idx];
+          R[idx] = r;
+        }
+        acc += r * r;
+      }
+    }
+    block_col_store(acc, m, partial);
+  }
+}
+
+__global__ void k_xpay(const double* __restrict__ R, int ldr, double* __restrict__ P, int ldp,
+                       int n, int b, const double* __restrict__ beta, int first) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * b) return;
+  const int64_t i = t / b, c = t % b;
+  const double r = R[i * ldr + c];
+  P[i * ldp + c] = first ? r : r + beta[c] * P[i * ldp + c];
+}
+
+__global__ void k_copy(const double* __restrict__ X, int ldx, double* __restrict__ Y, int ldy,
+                       int n, int b) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * b) return;
+  const int64_t i = t / b, c = t % b;
+  Y[i * ldy + c] = X[i * ldx + c];
+}
+
+__global__ void k_zero(double* __restrict__ Y, int ldy, int n, int b) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * b) return;
+  const int64_t i = t / b, c = t % b;
+  Y[i * ldy + c] = 0.0;
+}
+
+__global__ void k_scale_cols(const double* __restrict__ X, int ldx, const double* __restrict__ d,
+                             double* __restrict__ Y, int ldy, int n, int b, int acc) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * b) return;
+  const int64_t i = t / b, c = t % b;
+  const double v = X[i * ldx + c] * d[c];
+  if (acc)
+    Y[i * ldy + c] += v;
+  else
+    Y[i * ldy + c] = v;
+}
+
+__global__ void k_axpby(double a, const double* __restrict__ X, int ldx, double cc,
+                        double* __restrict__ Y, int ldy, int n, int b) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * b) return;
+  const int64_t i = t / b, c = t % b;
+  const double y = cc == 0.0 ? 0.0 : cc * Y[i * ldy + c];
+  Y[i * ldy + c] = a * X[i * ldx + c] + y;
+}
+
+__global__ void k_rsub(const double* __restrict__ B, int ldb, double* __restrict__ R, int ldr,
+                       int n, int b) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * b) return;
+  const int64_t i = t / b, c = t % b;
+  R[i * ldr + c] = B[i * ldb + c] - R[i * ldr + c];
+}
+
+__global__ void k_scale_vec_dev(const double* __restrict__ x, const double* __restrict__ sc,
+                                int inv_sqrt, double* __restrict__ y, int ldy, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double f = inv_sqrt ? 1.0 / sqrt(sc[0]) : 1.0 / sc[0];
+  y[(size_t)i * ldy] = x[i] * f;
+}
+
+__global__ void k_gather_cols(const double* __restrict__ Y, int ldy, const int* __restrict__ idx,
+                              double* __restrict__ Z, int ldz, int n, int b) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * b) return;
+  const int64_t i = t / b, c = t % b;
+  Z[i * ldz + c] = Y[i * ldy + idx[c]];
+}
+
+__global__ void k_to_colmajor(const double* __restrict__ X, int ldx,
+                              const double* __restrict__ scale, double* __restrict__ out, int n,
+                              int b) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * b) return;
+  const int64_t c = t / n, i = t % n;
+  out[c * n + i] = X[i * ldx + c] * scale[c];
+}
+
+__global__ void k_absmax_part(const double* __restrict__ X, int ldx, int n, int b, int chunk,
+                              int* __restrict__ pidx, double* __restrict__ pval) {
+  const int c = blockIdx.y * blockDim.x + threadIdx.x;
+  if (c >= b) return;
+  const int lo = blockIdx.x * chunk;
+  const int hi = min(n, lo + chunk);
+  double best = -1.0, bv = 0.0;
+  int bi = n;
+  for (int i = lo; i < hi; ++i) {
+    const double v = X[(size_t)i * ldx + c];
+    if (fabs(v) > best) {
+      best = fabs(v);
+      bv = v;
+      bi = i;
+    }
+  }
+  pidx[(size_t)blockIdx.x * b + c] = bi;
+  pval[(size_t)blockIdx.x * b + c] = bv;
+}
+
+__global__ void k_absmax_fin(const int* __restrict__ pidx, const double* __restrict__ pval,
+                             int nch, int b, int* __restrict__ idx, double* __restrict__ val) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= b) return;
+  double best = -1.0, bv = 0.0;
+  int bi = 0;
+  for (int q = 0; q < nch; ++q) {
+    const double v = pval[(size_t)q * b + c];
+    if (fabs(v) > best) {  // chunks in ascending row order: ties keep the lower index
+      best = fabs(v);
+      bv = v;
+      bi = pidx[(size_t)q * b + c];
+    }
+  }
+  idx[c] = bi;
+  val[c] = bv;
+}
+
+__global__ void k_i64_to_i32(const int64_t* __restrict__ src, int* __restrict__ dst, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) dst[t] = static_cast<int>(src[t]);
+}
+
+// ------------------------------------------------------------------ FP64 GEMMs
+// 64 x 64 output tile, 256 threads in a 16 x 16 grid, 4 x 4 outputs per thread
+// at stride 16 (conflict-free LDS reads), K staged 16 at a time through LDS.
+constexpr int TM = 64, TK = 16;
+
+__global__ __launch_bounds__(kBlock) void k_gram(const double* __restrict__ X, int ldx,
+                                                 const double* __restrict__ Y, int ldy, int n,
+                                                 int m, int p, int chunk,
+                                                 double* __restrict__ work) {
+  __shared__ double xs[TK][TM];
+  __shared__ double ys[TK][TM];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int i0 = blockIdx.x * TM, j0 = blockIdx.y * TM;
+  const int r0 = blockIdx.z * chunk;
+  const int r1 = min(n, r0 + chunk);
+  double acc[4][4] = {};
+  for (int k0 = r0; k0 < r1; k0 += TK) {
+    for (int q = threadIdx.x; q < TK * TM; q += kBlock) {
+      const int kk = q / TM, cc = q % TM;
+      const int row = k0 + kk;
+      xs[kk][cc] = (row < r1 && i0 + cc < m) ? X[(size_t)row * ldx + i0 + cc] : 0.0;
+      ys[kk][cc] = (row < r1 && j0 + cc < p) ? Y[(size_t)row * ldy + j0 + cc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TK; ++kk) {
+      double a[4], bb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = xs[kk][ty + 16 * u];
+        bb[u] = ys[kk][tx + 16 * u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * bb[v];
+    }
+    __syncthreads();
+  }
+  double* w = work + (size_t)blockIdx.z * m * p;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + ty + 16 * u, j = j0 + tx + 16 * v;
+      if (i < m && j < p) w[(size_t)i * p + j] = acc[u][v];
+    }
+}
+
+__global__ void k_gram_reduce(const double* __restrict__ work, int splits, int m, int p,
+                              double* __restrict__ C, int ldc) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)m * p) return;
+  double s = 0.0;
+  for (int q = 0; q < splits; ++q) s += work[(size_t)q * m * p + t];
+  C[(t / p) * ldc + (t % p)] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_gemm_nn(const double* __restrict__ X, int ldx,
+                                                    const double* __restrict__ C, int ldc,
+                                                    double* __restrict__ Z, int ldz, int n,
+                                                    int m, int p, double alpha, double beta) {
+  __shared__ double xs[TK][TM + 1];
+  __shared__ double cs[TK][TM];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int i0 = blockIdx.x * TM, j0 = blockIdx.y * TM;
+  double acc[4][4] = {};
+  for (int k0 = 0; k0 < m; k0 += TK) {
+    for (int q = threadIdx.x; q < TK * TM; q += kBlock) {
+      const int rr = q / TK, kk = q % TK;  // X tile: 64 rows x 16 k, k fastest
+      const int row = i0 + rr, k = k0 + kk;
+      xs[kk][rr] = (row < n && k < m) ? X[(size_t)row * ldx + k] : 0.0;
+      const int kc = q / TM, cc = q % TM;  // C tile: 16 k x 64 cols
+      const int k2 = k0 + kc, j = j0 + cc;
+      cs[kc][cc] = (k2 < m && j < p) ? C[(size_t)k2 * ldc + j] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TK; ++kk) {
+      double a[4], bb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = xs[kk][ty + 16 * u];
+        bb[u] = cs[kk][tx + 16 * u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * bb[v];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + ty + 16 * u, j = j0 + tx + 16 * v;
+      if (i < n && j < p) {
+        const size_t iz = (size_t)i * ldz + j;
+        const double old = beta == 0.0 ? 0.0 : beta * Z[iz];
+        Z[iz] = alpha * acc[u][v] + old;
+      }
+    }
+}
+
+__global__ void k_gemv_t(const double* __restrict__ X, int ldx, const double* __restrict__ y,
+                         int n, int m, int chunk, double* __restrict__ work) {
+  const int c = blockIdx.y * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+  double acc = 0.0;
+  for (int i = lo; i < hi; ++i) acc += X[(size_t)i * ldx + c] * y[i];
+  work[(size_t)blockIdx.x * m + c] = acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_gemv_n_sub(const double* __restrict__ X, int ldx,
+                                                       const double* __restrict__ h, int n,
+                                                       int m, double* __restrict__ z) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int row = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  if (row >= n) return;
+  double acc = 0.0;
+  for (int c = lane; c < m; c += kWave) acc += X[(size_t)row * ldx + c] * h[c];
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) acc += __shfl_xor(acc, off, kWave);
+  if (lane == 0) z[row] -= acc;
+}
+
+inline int red_grid(int n, int b) {
+  const int rows_per_block = b <= kBlock ? kBlock / b : 1;
+  const int want = ceil_div((int64_t)n, (int64_t)rows_per_block * 8);
+  return std::max(1, std::min(kRedBlocks, want));
+}
+
+inline int ew_grid(int64_t count) { return std::max(1, ceil_div(count, kBlock)); }
+
+}  // namespace
+
+// ======================================================================= launchers
+int spmm(const CsrView& A, const double* X, int ldx, double* Y, int ldy, int b, hipStream_t s,
+         bool fuse, bool first, const double* beta, double* P, int ldp, double* partial,
+         const double* dot_with, int ld_dot) {
+  if (A.n_rows == 0 || b == 0) return 0;
+  if (b == 1) {
+    if (A.avg_row <= 10.0) return launch_spmm_t<8, 1>(A, X, ldx, Y, ldy, b, s, fuse, first, beta, P, ldp, partial, dot_with, ld_dot);
+    if (A.avg_row <= 24.0) return launch_spmm_t<16, 1>(A, X, ldx, Y, ldy, b, s, fuse, first, beta, P, ldp, partial, dot_with, ld_dot);
+    return launch_spmm_t<64, 1>(A, X, ldx, Y, ldy, b, s, fuse, first, beta, P, ldp, partial, dot_with, ld_dot);
+  }
+  if (b <= 4) return launch_spmm_t<16, 4>(A, X, ldx, Y, ldy, b, s, fuse, first, beta, P, ldp, partial, dot_with, ld_dot);
+  if (b <= 32) return launch_spmm_t<4, 16>(A, X, ldx, Y, ldy, b, s, fuse, first, beta, P, ldp, partial, dot_with, ld_dot);
+  return launch_spmm_t<1, 64>(A, X, ldx, Y, ldy, b, s, fuse, first, beta, P, ldp, partial, dot_with, ld_dot);
+}
+
+void house_ut(const HouseView& H, const double* x, int ldx, double* y, int ldy, int b,
+              hipStream_t s) {
+  if (H.npatch == 0 || b == 0) return;
+  const int64_t cnt = (int64_t)H.npatch * b;
+  hipLaunchKernelGGL(k_house_ut, dim3(ew_grid(cnt)), dim3(kBlock), 0, s, H.npatch, H.ptr,
+                     H.members, H.u, H.scale, x, ldx, y, ldy, b);
+  check_launch();
+}
+
+void house_u(const HouseView& H, const double* y, int ldy, double* x, int ldx, int b,
+             hipStream_t s) {
+  if (H.npatch == 0 || b == 0) return;
+  const int64_t cnt = (int64_t)H.npatch * b;
+  hipLaunchKernelGGL(k_house_u, dim3(ew_grid(cnt)), dim3(kBlock), 0, s, H.npatch, H.ptr,
+                     H.members, H.u, H.scale, y, ldy, x, ldx, b);
+  check_launch();
+}
+
+int col_dot(const double* X, int ldx, const double* Y, int ldy, int n, int b, double* partial,
+            hipStream_t s) {
+  const int g = red_grid(n, b);
+  hipLaunchKernelGGL(k_coldot<0>, dim3(g), dim3(kBlock), 0, s, X, ldx, Y, nullptr, ldy, n, b,
+                     partial, nullptr);
+  check_launch();
+  return g;
+}
+
+int col_dot2(const double* X, int ldx, const double* Y1, const double* Y2, int ldy, int n,
+             int b, double* partial1, double* partial2, hipStream_t s) {
+  const int g = red_grid(n, b);
+  hipLaunchKernelGGL(k_coldot<1>, dim3(g), dim3(kBlock), 0, s, X, ldx, Y1, Y2, ldy, n, b,
+                     partial1, partial2);
+  check_launch();
+  return g;
+}
+
+void reduce_partials(const double* partial, int nblk, int b, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_partials, dim3(ceil_div(b, kBlock)), dim3(kBlock), 0, s, partial,
+                     nblk, b, out);
+  check_launch();
+}
+
+void cg_init(ColScalars sc, const double* part_bn, const double* part_rr, int nblk, int b,
+             double tol, const int* parent_active, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_init, dim3(ceil_div(b, kBlock)), dim3(kBlock), 0, s, sc, part_bn,
+                     part_rr, nblk, b, tol, parent_active);
+  check_launch();
+}
+
+void cg_alpha(ColScalars sc, const double* part_pq, int nblk, int b, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_alpha, dim3(ceil_div(b, kBlock)), dim3(kBlock), 0, s, sc, part_pq,
+                     nblk, b);
+  check_launch();
+}
+
+void cg_beta(ColScalars sc, const double* part_rr, int nblk, int b, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_beta, dim3(ceil_div(b, kBlock)), dim3(kBlock), 0, s, sc, part_rr,
+                     nblk, b);
+  check_launch();
+}
+
+void pcg_conv(ColScalars sc, const double* part_rr, int nblk, int b, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_conv, dim3(ceil_div(b, kBlock)), dim3(kBlock), 0, s, sc, part_rr,
+                     nblk, b);
+  check_launch();
+}
+
+void pcg_beta(ColScalars sc, const double* part_rz, const double* part_rzo, int nblk, int b,
+              hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_beta, dim3(ceil_div(b, kBlock)), dim3(kBlock), 0, s, sc, part_rz,
+                     part_rzo, nblk, b);
+  check_launch();
+}
+
+int cg_update(double* X, int ldx, double* R, const double* P, const double* Q, int ld, int n,
+              int b, const double* alpha, double* partial, hipStream_t s) {
+  const int g = red_grid(n, b);
+  hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(kBlock), 0, s, X, ldx, R, P, Q, ld, n, b, alpha,
+                     partial);
+  check_launch();
+  return g;
+}
+
+void xpay(const double* R, int ldr, double* P, int ldp, int n, int b, const double* beta,
+          bool first, hipStream_t s) {
+  if ((int64_t)n * b == 0) return;
+  hipLaunchKernelGGL(k_xpay, dim3(ew_grid((int64_t)n * b)), dim3(kBlock), 0, s, R, ldr, P, ldp,
+                     n, b, beta, first ? 1 : 0);
+  check_launch();
+}
+
+void copy_block(const double* X, int ldx, double* Y, int ldy, int n, int b, hipStream_t s) {
+  if ((int64_t)n * b == 0) return;
+  hipLaunchKernelGGL(k_copy, dim3(ew_grid((int64_t)n * b)), dim3(kBlock), 0, s, X, ldx, Y, ldy,
+                     n, b);
+  check_launch();
+}
+
+void zero_block(double* Y, int ldy, int n, int b, hipStream_t s) {
+  if ((int64_t)n * b == 0) return;
+  hipLaunchKernelGGL(k_zero, dim3(ew_grid((int64_t)n * b)), dim3(kBlock), 0, s, Y, ldy, n, b);
+  check_launch();
+}
+
+void scale_cols(const double* X, int ldx, const double* d, double* Y, int ldy, int n, int b,
+                bool accumulate, hipStream_t s) {
+  if ((int64_t)n * b == 0) return;
+  hipLaunchKernelGGL(k_scale_cols, dim3(ew_grid((int64_t)n * b)), dim3(kBlock), 0, s, X, ldx, d,
+                     Y, ldy, n, b, accumulate ? 1 : 0);
+  check_launch();
+}
+
+void axpby(double a, const double* X, int ldx, double c, double* Y, int ldy, int n, int b,
+           hipStream_t s) {
+  if ((int64_t)n * b == 0) return;
+  hipLaunchKernelGGL(k_axpby, dim3(ew_grid((int64_t)n * b)), dim3(kBlock), 0, s, a, X, ldx, c,
+                     Y, ldy, n, b);
+  check_launch();
+}
+
+void rsub(const double* B, int ldb, double* R, int ldr, int n, int b, hipStream_t s) {
+  if ((int64_t)n * b == 0) return;
+  hipLaunchKernelGGL(k_rsub, dim3(ew_grid((int64_t)n * b)), dim3(kBlock), 0, s, B, ldb, R, ldr,
+                     n, b);
+  check_launch();
+}
+
+void scale_vec_dev(const double* x, const double* scal, bool inv_sqrt, double* y, int ldy,
+                   int n, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_scale_vec_dev, dim3(ew_grid(n)), dim3(kBlock), 0, s, x, scal,
+                     inv_sqrt ? 1 : 0, y, ldy, n);
+  check_launch();
+}
+
+void gather_cols(const double* Y, int ldy, const int* idx, double* Z, int ldz, int n, int b,
+                 hipStream_t s) {
+  if ((int64_t)n * b == 0) return;
+  hipLaunchKernelGGL(k_gather_cols, dim3(ew_grid((int64_t)n * b)), dim3(kBlock), 0, s, Y, ldy,
+                     idx, Z, ldz, n, b);
+  check_launch();
+}
+
+void to_colmajor(const double* X, int ldx, const double* colscale, double* out, int n, int b,
+                 hipStream_t s) {
+  if ((int64_t)n * b == 0) return;
+  hipLaunchKernelGGL(k_to_colmajor, dim3(ew_grid((int64_t)n * b)), dim3(kBlock), 0, s, X, ldx,
+                     colscale, out, n, b);
+  check_launch();
+}
+
+void col_absmax(const double* X, int ldx, int n, int b, int* idx, double* val, hipStream_t s) {
+  // partial results live in the tail of the output-sized scratch the caller owns
+  static thread_local DBuf<int> pidx;
+  static thread_local DBuf<double> pval;
+  const int chunk = std::max(256, ceil_div(n, 256));
+  const int nch = ceil_div(n, chunk);
+  pidx.ensure((size_t)nch * b);
+  pval.ensure((size_t)nch * b);
+  hipLaunchKernelGGL(k_absmax_part, dim3(nch, ceil_div(b, kBlock)), dim3(kBlock), 0, s, X, ldx,
+                     n, b, chunk, pidx.p, pval.p);
+  check_launch();
+  hipLaunchKernelGGL(k_absmax_fin, dim3(ceil_div(b, kBlock)), dim3(kBlock), 0, s, pidx.p,
+                     pval.p, nch, b, idx, val);
+  check_launch();
+}
+
+void i64_to_i32(const int64_t* src, int* dst, int64_t n, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_i64_to_i32, dim3(ew_grid(n)), dim3(kBlock), 0, s, src, dst, n);
+  check_launch();
+}
+
+static int gram_splits(int n, int m, int p) {
+  const int tiles = ceil_div(m, TM) * ceil_div(p, TM);
+  int splits = std::max(1, 1024 / std::max(1, tiles));
+  splits = std::min(splits, std::max(1, ceil_div(n, 256)));
+  return splits;
+}
+
+size_t gram_work_size(int n, int m, int p) {
+  return (size_t)gram_splits(n, m, p) * m * p;
+}
+
+void gram(const double* X, int ldx, const double* Y, int ldy, int n, int m, int p, double* C,
+          int ldc, double* work, hipStream_t s) {
+  if (m == 0 || p == 0) return;
+  const int splits = gram_splits(n, m, p);
+  const int chunk = ceil_div(n, splits);
+  hipLaunchKernelGGL(k_gram, dim3(ceil_div(m, TM), ceil_div(p, TM), splits), dim3(kBlock), 0, s,
+                     X, ldx, Y, ldy, n, m, p, chunk, work);
+  check_launch();
+  hipLaunchKernelGGL(k_gram_reduce, dim3(ew_grid((int64_t)m * p)), dim3(kBlock), 0, s, work,
+                     splits, m, p, C, ldc);
+  check_launch();
+}
+
+void gemm_nn(const double* X, int ldx, const double* C, int ldc, double* Z, int ldz, int n,
+             int m, int p, double alpha, double beta, hipStream_t s) {
+  if (n == 0 || p == 0) return;
+  hipLaunchKernelGGL(k_gemm_nn, dim3(ceil_div(n, TM), ceil_div(p, TM)), dim3(kBlock), 0, s, X,
+                     ldx, C, ldc, Z, ldz, n, m, p, alpha, beta);
+  check_launch();
+}
+
+void gemv_t(const double* X, int ldx, const double* y, int n, int m, double* h, double* work,
+            hipStream_t s) {
+  if (m == 0) return;
+  const int chunk = std::max(64, ceil_div(n, 256));
+  const int nch = ceil_div(n, chunk);
+  hipLaunchKernelGGL(k_gemv_t, dim3(nch, ceil_div(m, kBlock)), dim3(kBlock), 0, s, X, ldx, y, n,
+                     m, chunk, work);
+  check_launch();
+  reduce_partials(work, nch, m, h, s);
+}
+
+void gemv_n_sub(const double* X, int ldx, const double* h, int n, int m, double* z,
+                hipStream_t s) {
+  if (m == 0 || n == 0) return;
+  hipLaunchKernelGGL(k_gemv_n_sub, dim3(ceil_div(n, kBlock / kWave)), dim3(kBlock), 0, s, X, ldx,
+                     h, n, m, z);
+  check_launch();
+}
+
+}  // namespace mmd

@@ -1,0 +1,699 @@
+// Host construction of the multiresolution matrix decomposition
+// (Sections 2.1-2.3): partition, local basis phi (q = 1), Householder
+// complement U, localised Psi (constrained-energy form, Appendix A),
+// Galerkin level operators A^(k), M^(k), and their upload to the device.
+#include <omp.h>
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+#include <numeric>
+#include <string>
+
+#include "dense.h"
+#include "handle.h"
+
+namespace mmd {
+
+namespace {
+
+// ---------------------------------------------------------------- input checks
+void validate_and_copy(const mmd_csr& in, HostCSR& A, std::vector<double>& s) {
+  MMD_REQUIRE(in.n > 0 && in.n < (int64_t(1) << 31), MMD_EINVAL, "n out of range");
+  MMD_REQUIRE(in.nnz >= in.n && in.nnz < (int64_t(1) << 31), MMD_EINVAL, "nnz out of range");
+  const int n = static_cast<int>(in.n);
+  A.n_rows = A.n_cols = n;
+  A.ptr.resize(n + 1);
+  A.col.resize(in.nnz);
+  A.val.resize(in.nnz);
+  if (in.mem == 1) {
+    MMD_HIP(hipMemcpy(A.ptr.data(), in.rowptr, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+    MMD_HIP(hipMemcpy(A.col.data(), in.colind, in.nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+    MMD_HIP(hipMemcpy(A.val.data(), in.val, in.nnz * sizeof(double), hipMemcpyDeviceToHost));
+  } else {
+    std::copy(in.rowptr, in.rowptr + n + 1, A.ptr.begin());
+    std::copy(in.colind, in.colind + in.nnz, A.col.begin());
+    std::copy(in.val, in.val + in.nnz, A.val.begin());
+  }
+  MMD_REQUIRE(A.ptr[0] == 0 && A.ptr[n] == in.nnz, MMD_EINVAL, "rowptr does not span nnz");
+  s.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    MMD_REQUIRE(A.ptr[i] <= A.ptr[i + 1], MMD_EINVAL, "rowptr not monotone");
+    double diag = 0.0, off = 0.0;
+    bool has_diag = false;
+    for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+      const int j = A.col[k];
+      const double v = A.val[k];
+      MMD_REQUIRE(j >= 0 && j < n, MMD_EINVAL, "column index out of range");
+      MMD_REQUIRE(k == A.ptr[i] || A.col[k - 1] < j, MMD_EINVAL, "columns not sorted/unique");
+      MMD_REQUIRE(std::isfinite(v), MMD_EINVAL, "non-finite value");
+      if (j == i) {
+        diag = v;
+        has_diag = true;
+      } else {
+        MMD_REQUIRE(v <= 0.0, MMD_EUNSUPPORTED,
+                    "positive off-diagonal: no edge-type energy decomposition");
+        off += v;
+        // symmetric counterpart
+        auto b = A.col.begin() + A.ptr[j], e = A.col.begin() + A.ptr[j + 1];
+        auto it = std::lower_bound(b, e, i);
+        MMD_REQUIRE(it != e && *it == i && A.val[it - A.col.begin()] == v, MMD_EINVAL,
+                    "matrix is not symmetric");
+      }
+    }
+    MMD_REQUIRE(has_diag && diag > 0.0, MMD_ENOTSPD, "nonpositive diagonal entry");
+    double si = diag + off;
+    MMD_REQUIRE(si >= -1e-14 * diag, MMD_EUNSUPPORTED,
+                "negative self-loop weight (not diagonally dominant)");
+    s[i] = si < 0.0 ? 0.0 : si;
+  }
+}
+
+// ---------------------------------------------------------------- partitions
+using Patches = std::vector<std::vector<int>>;
+
+Patches grid_patches(const std::vector<int>& shape, int blk, std::vector<int>& cshape) {
+  const int d = static_cast<int>(shape.size());
+  cshape.resize(d);
+  for (int a = 0; a < d; ++a) cshape[a] = (shape[a] + blk - 1) / blk;
+  int np = 1;
+  for (int a = 0; a < d; ++a) np *= cshape[a];
+  Patches P(np);
+  const int nx = shape[0], ny = shape[1], nz = d == 3 ? shape[2] : 1;
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const int v = (z * ny + y) * nx + x;
+        int pid = (y / blk) * cshape[0] + (x / blk);
+        if (d == 3) pid = ((z / blk) * cshape[1] + (y / blk)) * cshape[0] + (x / blk);
+        P[pid].push_back(v);  // ascending vertex order by construction
+      }
+  return P;
+}
+
+std::vector<int> morton_order(const std::vector<double>& xyz, int n, int d) {
+  const int bits = d == 2 ? 16 : 10;
+  const double scale = static_cast<double>(1 << bits);
+  std::vector<int64_t> code(n, 0);
+  for (int a = 0; a < d; ++a) {
+    double lo = std::numeric_limits<double>::infinity(), hi = -lo;
+    for (int i = 0; i < n; ++i) {
+      lo = std::min(lo, xyz[(size_t)i * d + a]);
+      hi = std::max(hi, xyz[(size_t)i * d + a]);
+    }
+    if (!(hi > lo)) continue;
+    for (int i = 0; i < n; ++i) {
+      double t = std::floor((xyz[(size_t)i * d + a] - lo) / (hi - lo) * scale);
+      int64_t q = static_cast<int64_t>(std::min(std::max(t, 0.0), scale - 1.0));
+      for (int b = 0; b < bits; ++b) code[i] |= ((q >> b) & 1) << (d * b + a);
+    }
+  }
+  std::vector<int> ord(n);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return code[x] < code[y]; });
+  return ord;
+}
+
+// Greedy breadth-first aggregation in Morton order, then merge of patches
+// smaller than target/2 into the neighbour sharing the most entries.
+Patches greedy_patches(const HostCSR& A, const std::vector<double>& xyz, int d, int target) {
+  const int n = A.n_rows;
+  std::vector<int> order;
+  if (d > 0) order = morton_order(xyz, n, d);
+  else {
+    order.resize(n);
+    std::iota(order.begin(), order.end(), 0);
+  }
+  std::vector<int> pid(n, -1);
+  Patches P;
+  for (int s : order) {
+    if (pid[s] >= 0) continue;
+    const int cur = static_cast<int>(P.size());
+    std::vector<int> mem{s};
+    pid[s] = cur;
+    size_t head = 0;
+    while (head < mem.size() && static_cast<int>(mem.size()) < target) {
+      const int v = mem[head++];
+      for (int64_t k = A.ptr[v]; k < A.ptr[v + 1]; ++k) {
+        const int u = A.col[k];
+        if (pid[u] < 0) {
+          pid[u] = cur;
+          mem.push_back(u);
+          if (static_cast<int>(mem.size()) >= target) break;
+        }
+      }
+    }
+    P.push_back(std::move(mem));
+  }
+  for (size_t p = 0; p < P.size(); ++p) {
+    if (P[p].empty() || 2 * static_cast<int>(P[p].size()) >= target) continue;
+    std::vector<std::pair<int, int>> cnt;  // (patch, count), small
+    for (int v : P[p])
+      for (int64_t k = A.ptr[v]; k < A.ptr[v + 1]; ++k) {
+        const int q = pid[A.col[k]];
+        if (q == static_cast<int>(p)) continue;
+        auto it = std::find_if(cnt.begin(), cnt.end(), [&](auto& c) { return c.first == q; });
+        if (it == cnt.end()) cnt.emplace_back(q, 1);
+        else it->second++;
+      }
+    if (cnt.empty()) continue;
+    int best = -1, bc = -1;
+    for (auto& c : cnt)
+      if (c.second > bc || (c.second == bc && c.first < best)) {
+        best = c.first;
+        bc = c.second;
+      }
+    for (int v : P[p]) pid[v] = best;
+    P[best].insert(P[best].end(), P[p].begin(), P[p].end());
+    P[p].clear();
+  }
+  Patches out;
+  for (auto& m : P)
+    if (!m.empty()) {
+      std::sort(m.begin(), m.end());
+      out.push_back(std::move(m));
+    }
+  return out;
+}
+
+// ---------------------------------------------------------------- patch energies
+// Interior energy (level 1, generalised edges inside P + clamped remainder)
+// or closed energy (levels >= 2, principal submatrix).
+std::vector<double> patch_energy(const HostCSR& A, const std::vector<int>& mem, bool closed) {
+  const int p = static_cast<int>(mem.size());
+  std::vector<double> E((size_t)p * p, 0.0);
+  for (int a = 0; a < p; ++a) {
+    const int i = mem[a];
+    double diag = 0.0, offabs = 0.0, inner = 0.0;
+    for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+      const int c = A.col[k];
+      const double v = A.val[k];
+      if (c == i) {
+        diag += v;
+        continue;
+      }
+      offabs += std::fabs(v);
+      auto it = std::lower_bound(mem.begin(), mem.end(), c);
+      if (it != mem.end() && *it == c) {
+        E[(size_t)a * p + (it - mem.begin())] = v;
+        inner += std::fabs(v);
+      }
+    }
+    E[(size_t)a * p + a] = closed ? diag : inner + std::max(diag - offabs, 0.0);
+  }
+  return E;
+}
+
+// ---------------------------------------------------------------- sparse helpers
+HostCSR transpose(const HostCSR& X) {
+  HostCSR T;
+  T.n_rows = X.n_cols;
+  T.n_cols = X.n_rows;
+  T.ptr.assign(T.n_rows + 1, 0);
+  for (int64_t k = 0; k < X.nnz(); ++k) T.ptr[X.col[k] + 1]++;
+  for (int i = 0; i < T.n_rows; ++i) T.ptr[i + 1] += T.ptr[i];
+  T.col.resize(X.nnz());
+  T.val.resize(X.nnz());
+  std::vector<int64_t> pos(T.ptr.begin(), T.ptr.end() - 1);
+  for (int i = 0; i < X.n_rows; ++i)
+    for (int64_t k = X.ptr[i]; k < X.ptr[i + 1]; ++k) {
+      const int64_t q = pos[X.col[k]]++;
+      T.col[q] = i;
+      T.val[q] = X.val[k];
+    }
+  return T;
+}
+
+// Z = X * Y with the structural pattern (every touched column is kept).
+HostCSR spgemm(const HostCSR& X, const HostCSR& Y) {
+  HostCSR Z;
+  Z.n_rows = X.n_rows;
+  Z.n_cols = Y.n_cols;
+  const int nr = X.n_rows;
+  std::vector<std::vector<int>> rc(nr);
+  std::vector<std::vector<double>> rv(nr);
+#pragma omp parallel
+  {
+    std::vector<double> acc(Y.n_cols, 0.0);
+    std::vector<char> mark(Y.n_cols, 0);
+    std::vector<int> cols;
+#pragma omp for schedule(dynamic, 64)
+    for (int i = 0; i < nr; ++i) {
+      cols.clear();
+      for (int64_t k = X.ptr[i]; k < X.ptr[i + 1]; ++k) {
+        const int r = X.col[k];
+        const double xv = X.val[k];
+        for (int64_t q = Y.ptr[r]; q < Y.ptr[r + 1]; ++q) {
+          const int c = Y.col[q];
+          if (!mark[c]) {
+            mark[c] = 1;
+            cols.push_back(c);
+          }
+          acc[c] += xv * Y.val[q];
+        }
+      }
+      std::sort(cols.begin(), cols.end());
+      rc[i] = cols;
+      rv[i].resize(cols.size());
+      for (size_t t = 0; t < cols.size(); ++t) {
+        rv[i][t] = acc[cols[t]];
+        acc[cols[t]] = 0.0;
+        mark[cols[t]] = 0;
+      }
+    }
+  }
+  Z.ptr.assign(nr + 1, 0);
+  for (int i = 0; i < nr; ++i) Z.ptr[i + 1] = Z.ptr[i] + static_cast<int64_t>(rc[i].size());
+  Z.col.resize(Z.ptr[nr]);
+  Z.val.resize(Z.ptr[nr]);
+  for (int i = 0; i < nr; ++i) {
+    std::copy(rc[i].begin(), rc[i].end(), Z.col.begin() + Z.ptr[i]);
+    std::copy(rv[i].begin(), rv[i].end(), Z.val.begin() + Z.ptr[i]);
+  }
+  return Z;
+}
+
+// 0.5 (C + C^T) on C's (structurally symmetric) pattern.
+void symmetrize(HostCSR& C) {
+  std::vector<double> out(C.val.size());
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int i = 0; i < C.n_rows; ++i)
+    for (int64_t k = C.ptr[i]; k < C.ptr[i + 1]; ++k) {
+      const int j = C.col[k];
+      auto b = C.col.begin() + C.ptr[j], e = C.col.begin() + C.ptr[j + 1];
+      auto it = std::lower_bound(b, e, i);
+      const double cji = (it != e && *it == i) ? C.val[it - C.col.begin()] : 0.0;
+      out[k] = 0.5 * (C.val[k] + cji);
+    }
+  C.val.swap(out);
+}
+
+// Psi^T X Psi (X == nullptr: identity), symmetrised.
+HostCSR galerkin(const HostCSR& Psi, const HostCSR* X) {
+  HostCSR Pt = transpose(Psi);
+  HostCSR C = X ? spgemm(Pt, spgemm(*X, Psi)) : spgemm(Pt, Psi);
+  symmetrize(C);
+  return C;
+}
+
+double gershgorin(const HostCSR& M) {
+  double best = 0.0;
+  for (int i = 0; i < M.n_rows; ++i) {
+    double s = 0.0;
+    for (int64_t k = M.ptr[i]; k < M.ptr[i + 1]; ++k) s += std::fabs(M.val[k]);
+    best = std::max(best, s);
+  }
+  return best;
+}
+
+// dense principal submatrix A[S, S] (S sorted)
+void dense_sub(const HostCSR& A, const std::vector<int>& S, std::vector<double>& D) {
+  const int m = static_cast<int>(S.size());
+  D.assign((size_t)m * m, 0.0);
+  for (int a = 0; a < m; ++a) {
+    const int i = S[a];
+    int64_t k = A.ptr[i];
+    const int64_t ke = A.ptr[i + 1];
+    int b = 0;
+    while (k < ke && b < m) {  // merge of two sorted lists
+      if (A.col[k] == S[b]) {
+        D[(size_t)a * m + b] = A.val[k];
+        ++k;
+        ++b;
+      } else if (A.col[k] < S[b]) {
+        ++k;
+      } else {
+        ++b;
+      }
+    }
+  }
+}
+
+// solve (R^T R) X = B in place for nrhs columns of the row-major m x nrhs B
+void chol_solve(int m, const std::vector<double>& R, double* B, int nrhs) {
+  for (int c = 0; c < nrhs; ++c) {
+    for (int i = 0; i < m; ++i) {  // R^T y = b
+      double s = B[(size_t)i * nrhs + c];
+      for (int k = 0; k < i; ++k) s -= R[(size_t)k * m + i] * B[(size_t)k * nrhs + c];
+      B[(size_t)i * nrhs + c] = s / R[(size_t)i * m + i];
+    }
+    for (int i = m - 1; i >= 0; --i) {  // R x = y
+      double s = B[(size_t)i * nrhs + c];
+      for (int k = i + 1; k < m; ++k) s -= R[(size_t)i * m + k] * B[(size_t)k * nrhs + c];
+      B[(size_t)i * nrhs + c] = s / R[(size_t)i * m + i];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- Psi
+HostCSR psi_exact(const HostCSR& A, const Patches& P, const std::vector<double>& phi,
+                  const std::vector<int>& pptr) {
+  const int n = A.n_rows, m = static_cast<int>(P.size());
+  std::vector<int> all(n);
+  std::iota(all.begin(), all.end(), 0);
+  std::vector<double> D;
+  dense_sub(A, all, D);
+  std::vector<double> R;
+  MMD_REQUIRE(dense::cholesky_upper(n, D.data(), R), MMD_ENOTSPD, "level matrix not SPD");
+  std::vector<double> Y((size_t)n * m, 0.0);
+  for (int j = 0; j < m; ++j)
+    for (size_t t = 0; t < P[j].size(); ++t) Y[(size_t)P[j][t] * m + j] = phi[pptr[j] + t];
+  std::vector<double> Phi = Y;
+  chol_solve(n, R, Y.data(), m);
+  std::vector<double> G((size_t)m * m, 0.0);
+  for (int a = 0; a < m; ++a)
+    for (int b = 0; b < m; ++b) {
+      double s = 0.0;
+      for (size_t t = 0; t < P[a].size(); ++t)
+        s += phi[pptr[a] + t] * Y[(size_t)P[a][t] * m + b];
+      G[(size_t)a * m + b] = s;
+    }
+  for (int a = 0; a < m; ++a)
+    for (int b = a + 1; b < m; ++b) {
+      const double v = 0.5 * (G[(size_t)a * m + b] + G[(size_t)b * m + a]);
+      G[(size_t)a * m + b] = G[(size_t)b * m + a] = v;
+    }
+  std::vector<double> RG;
+  MMD_REQUIRE(dense::cholesky_upper(m, G.data(), RG), MMD_ENOTSPD, "Phi^T A^-1 Phi not SPD");
+  // Psi = Y G^-1 : rows of Psi^T = G^-1 Y^T -> solve G Z = Y^T (columns = rows of Y)
+  std::vector<double> Yt((size_t)m * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < m; ++j) Yt[(size_t)j * n + i] = Y[(size_t)i * m + j];
+  chol_solve(m, RG, Yt.data(), n);
+  HostCSR Psi;
+  Psi.n_rows = n;
+  Psi.n_cols = m;
+  Psi.ptr.resize(n + 1);
+  Psi.col.resize((size_t)n * m);
+  Psi.val.resize((size_t)n * m);
+  for (int i = 0; i <= n; ++i) Psi.ptr[i] = (int64_t)i * m;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < m; ++j) {
+      Psi.col[(size_t)i * m + j] = j;
+      Psi.val[(size_t)i * m + j] = Yt[(size_t)j * n + i];
+    }
+  (void)Phi;
+  return Psi;
+}
+
+HostCSR psi_localized(const HostCSR& A, const Patches& P, const std::vector<double>& phi,
+                      const std::vector<int>& pptr, int r_hops) {
+  const int n = A.n_rows, m = static_cast<int>(P.size());
+  std::vector<int> pid(n);
+  for (int j = 0; j < m; ++j)
+    for (int v : P[j]) pid[v] = j;
+  std::vector<std::vector<int>> nbr(m);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int j = 0; j < m; ++j) {
+    std::vector<int> s;
+    for (int v : P[j])
+      for (int64_t k = A.ptr[v]; k < A.ptr[v + 1]; ++k) {
+        const int q = pid[A.col[k]];
+        if (q != j) s.push_back(q);
+      }
+    std::sort(s.begin(), s.end());
+    s.erase(std::unique(s.begin(), s.end()), s.end());
+    nbr[j] = std::move(s);
+  }
+  std::vector<std::vector<int>> cols(m);  // support rows of column j
+  std::vector<std::vector<double>> vals(m);
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 8) reduction(+ : bad)
+  for (int j = 0; j < m; ++j) {
+    // patches within r hops
+    std::vector<int> C{j}, frontier{j};
+    std::vector<int> seen{j};
+    for (int h = 0; h < r_hops; ++h) {
+      std::vector<int> nxt;
+      for (int a : frontier)
+        for (int b : nbr[a])
+          if (std::find(seen.begin(), seen.end(), b) == seen.end()) {
+            seen.push_back(b);
+            nxt.push_back(b);
+          }
+      frontier.swap(nxt);
+    }
+    C = seen;
+    std::sort(C.begin(), C.end());
+    std::vector<int> S;
+    for (int a : C) S.insert(S.end(), P[a].begin(), P[a].end());
+    std::sort(S.begin(), S.end());
+    const int ms = static_cast<int>(S.size()), mc = static_cast<int>(C.size());
+    std::vector<double> D;
+    dense_sub(A, S, D);
+    std::vector<double> R;
+    if (!dense::cholesky_upper(ms, D.data(), R)) {
+      bad += 1;
+      continue;
+    }
+    std::vector<double> Y((size_t)ms * mc, 0.0);
+    for (int b = 0; b < mc; ++b) {
+      const int a = C[b];
+      for (size_t t = 0; t < P[a].size(); ++t) {
+        const int pos = static_cast<int>(std::lower_bound(S.begin(), S.end(), P[a][t]) - S.begin());
+        Y[(size_t)pos * mc + b] = phi[pptr[a] + t];
+      }
+    }
+    std::vector<double> PhiC = Y;
+    chol_solve(ms, R, Y.data(), mc);
+    std::vector<double> G((size_t)mc * mc, 0.0);
+    for (int a = 0; a < mc; ++a)
+      for (int b = 0; b < mc; ++b) {
+        double s = 0.0;
+        for (int i = 0; i < ms; ++i) s += PhiC[(size_t)i * mc + a] * Y[(size_t)i * mc + b];
+        G[(size_t)a * mc + b] = s;
+      }
+    for (int a = 0; a < mc; ++a)
+      for (int b = a + 1; b < mc; ++b) {
+        const double v = 0.5 * (G[(size_t)a * mc + b] + G[(size_t)b * mc + a]);
+        G[(size_t)a * mc + b] = G[(size_t)b * mc + a] = v;
+      }
+    std::vector<double> RG;
+    if (!dense::cholesky_upper(mc, G.data(), RG)) {
+      bad += 1;
+      continue;
+    }
+    std::vector<double> e(mc, 0.0);
+    e[std::lower_bound(C.begin(), C.end(), j) - C.begin()] = 1.0;
+    chol_solve(mc, RG, e.data(), 1);
+    std::vector<double> psi(ms, 0.0);
+    for (int i = 0; i < ms; ++i) {
+      double s = 0.0;
+      for (int b = 0; b < mc; ++b) s += Y[(size_t)i * mc + b] * e[b];
+      psi[i] = s;
+    }
+    cols[j] = std::move(S);
+    vals[j] = std::move(psi);
+  }
+  MMD_REQUIRE(bad == 0, MMD_ENOTSPD, "local KKT system not positive definite");
+  // assemble column lists into CSR (rows = fine dofs)
+  HostCSR PsiT;
+  PsiT.n_rows = m;
+  PsiT.n_cols = n;
+  PsiT.ptr.assign(m + 1, 0);
+  for (int j = 0; j < m; ++j) PsiT.ptr[j + 1] = PsiT.ptr[j] + static_cast<int64_t>(cols[j].size());
+  PsiT.col.resize(PsiT.ptr[m]);
+  PsiT.val.resize(PsiT.ptr[m]);
+  for (int j = 0; j < m; ++j) {
+    std::copy(cols[j].begin(), cols[j].end(), PsiT.col.begin() + PsiT.ptr[j]);
+    std::copy(vals[j].begin(), vals[j].end(), PsiT.val.begin() + PsiT.ptr[j]);
+  }
+  return transpose(PsiT);
+}
+
+}  // namespace
+
+// ======================================================================= build
+void build_hierarchy(mmd_handle& h, const mmd_csr& in, const mmd_build_opts& o) {
+  const int levels = o.levels > 0 ? o.levels : (o.levels < 0 ? 0 : 3);
+  std::vector<int> targets, blocks;
+  if (o.n_targets > 0) targets.assign(o.targets, o.targets + std::min(o.n_targets, 8));
+  else targets = {4, 8};
+  if (o.n_grid_blocks > 0) blocks.assign(o.grid_blocks, o.grid_blocks + std::min(o.n_grid_blocks, 8));
+  else blocks = {4, 2};
+  const int r_hops = o.r_hops > 0 ? o.r_hops : 1;
+  const int min_coarse = o.min_coarse > 0 ? o.min_coarse : 4;
+  MMD_REQUIRE(levels < MMD_MAX_LEVELS, MMD_EINVAL, "too many levels");
+  for (int t : targets) MMD_REQUIRE(t >= 2, MMD_EINVAL, "patch target must be >= 2");
+  for (int t : blocks) MMD_REQUIRE(t >= 2, MMD_EINVAL, "grid block must be >= 2");
+
+  h.host.clear();
+  h.host.emplace_back();
+  LevelHost& L0 = h.host[0];
+  validate_and_copy(in, L0.A, L0.s);
+  L0.n = L0.A.n_rows;
+  h.n = L0.n;
+  if (in.coords && in.coord_dim > 0) {
+    MMD_REQUIRE(in.coord_dim == 2 || in.coord_dim == 3, MMD_EINVAL, "coord_dim must be 2 or 3");
+    L0.cdim = in.coord_dim;
+    L0.coords.assign(in.coords, in.coords + (size_t)L0.n * in.coord_dim);
+  }
+  if (in.grid_dim > 0) {
+    MMD_REQUIRE(in.grid_dim == 2 || in.grid_dim == 3, MMD_EINVAL, "grid_dim must be 2 or 3");
+    int64_t prod = 1;
+    for (int a = 0; a < in.grid_dim; ++a) {
+      MMD_REQUIRE(in.grid[a] > 0, MMD_EINVAL, "grid extent must be positive");
+      prod *= in.grid[a];
+    }
+    MMD_REQUIRE(prod == L0.n, MMD_EINVAL, "grid shape does not match n");
+    L0.grid.assign(in.grid, in.grid + in.grid_dim);
+  }
+  h.eps.assign(1, 0.0);
+
+  for (int k = 1; k <= levels; ++k) {
+    const LevelHost& prev = h.host[k - 1];
+    const HostCSR& Ak = prev.A;
+    Patches P;
+    std::vector<int> cgrid;
+    if (!prev.grid.empty()) {
+      const int blk = blocks[std::min<size_t>(k - 1, blocks.size() - 1)];
+      P = grid_patches(prev.grid, blk, cgrid);
+    } else {
+      const int tgt = targets[std::min<size_t>(k - 1, targets.size() - 1)];
+      P = greedy_patches(Ak, prev.coords, prev.cdim, tgt);
+    }
+    const int np = static_cast<int>(P.size());
+    if (np >= prev.n || np < min_coarse) break;
+
+    LevelHost L;
+    L.n = np;
+    L.patch_ptr.assign(np + 1, 0);
+    for (int j = 0; j < np; ++j) L.patch_ptr[j + 1] = L.patch_ptr[j] + static_cast<int>(P[j].size());
+    L.members.resize(L.patch_ptr[np]);
+    for (int j = 0; j < np; ++j) std::copy(P[j].begin(), P[j].end(), L.members.begin() + L.patch_ptr[j]);
+    L.phi.assign(L.members.size(), 0.0);
+    L.hh_u.assign(L.members.size(), 0.0);
+    L.hh_scale.assign(np, 0.0);
+    L.eps_patch.assign(np, 0.0);
+    const bool closed = k >= 2;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int j = 0; j < np; ++j) {
+      const int p = static_cast<int>(P[j].size());
+      const int off = L.patch_ptr[j];
+      if (p == 1) {
+        L.phi[off] = 1.0;
+        L.eps_patch[j] = 0.0;
+      } else {
+        std::vector<double> E = patch_energy(Ak, P[j], closed);
+        std::vector<double> w, Z;
+        dense::sym_eig(p, E.data(), w, &Z);
+        double sum = 0.0;
+        for (int i = 0; i < p; ++i) sum += Z[(size_t)i * p];
+        double sg = 1.0;
+        if (sum < 0) sg = -1.0;
+        else if (sum == 0) {
+          for (int i = 0; i < p; ++i)
+            if (Z[(size_t)i * p] != 0) {
+              sg = Z[(size_t)i * p] < 0 ? -1.0 : 1.0;
+              break;
+            }
+        }
+        for (int i = 0; i < p; ++i) L.phi[off + i] = sg * Z[(size_t)i * p];
+        L.eps_patch[j] = w[1] > 0 ? 1.0 / w[1] : std::numeric_limits<double>::infinity();
+      }
+      double uu = 0.0;
+      for (int i = 0; i < p; ++i) {
+        double u = L.phi[off + i];
+        if (i == 0) u += L.phi[off] >= 0 ? 1.0 : -1.0;
+        L.hh_u[off + i] = u;
+        uu += u * u;
+      }
+      L.hh_scale[j] = 2.0 / uu;
+    }
+    L.eps_level = 0.0;
+    for (double e : L.eps_patch) L.eps_level = std::max(L.eps_level, e);
+    if (prev.n <= o.exact_max_n)
+      L.Psi = psi_exact(Ak, P, L.phi, L.patch_ptr);
+    else
+      L.Psi = psi_localized(Ak, P, L.phi, L.patch_ptr, r_hops);
+    L.A = galerkin(L.Psi, &Ak);
+    L.M = galerkin(L.Psi, k == 1 ? nullptr : &prev.M);
+    L.lam_max_M = gershgorin(L.M);
+    if (prev.cdim > 0) {
+      L.cdim = prev.cdim;
+      L.coords.assign((size_t)np * prev.cdim, 0.0);
+      for (int j = 0; j < np; ++j) {
+        for (int a = 0; a < prev.cdim; ++a) {
+          double s = 0.0;
+          for (int v : P[j]) s += prev.coords[(size_t)v * prev.cdim + a];
+          L.coords[(size_t)j * prev.cdim + a] = s / static_cast<double>(P[j].size());
+        }
+      }
+    }
+    L.grid = cgrid;
+    h.host.push_back(std::move(L));
+    h.eps.push_back(h.eps.back() + h.host.back().eps_level);
+  }
+  h.K = static_cast<int>(h.host.size()) - 1;
+}
+
+namespace {
+void upload_csr(const HostCSR& X, DBuf<int>& ptr, DBuf<int>& col, DBuf<double>& val,
+                CsrView& v, hipStream_t s) {
+  MMD_REQUIRE(X.nnz() < (int64_t(1) << 31), MMD_EINVAL, "level operator exceeds 2^31 entries");
+  std::vector<int> p32(X.ptr.begin(), X.ptr.end());
+  ptr.upload(p32, s);
+  col.upload(X.col, s);
+  val.upload(X.val, s);
+  v.n_rows = X.n_rows;
+  v.n_cols = X.n_cols;
+  v.nnz = X.nnz();
+  v.rowptr = ptr.p;
+  v.col = col.p;
+  v.val = val.p;
+  v.diag = nullptr;
+  v.avg_row = X.n_rows ? static_cast<double>(X.nnz()) / X.n_rows : 1.0;
+}
+}  // namespace
+
+void upload_hierarchy(mmd_handle& h, hipStream_t s) {
+  h.dev.clear();
+  h.dev.resize(h.host.size());
+  // level 0: edge form (off-diagonal weights w = -a_ij and self-loops s)
+  {
+    const LevelHost& L0 = h.host[0];
+    LevelDev& D0 = h.dev[0];
+    HostCSR W;
+    W.n_rows = W.n_cols = L0.n;
+    W.ptr.assign(L0.n + 1, 0);
+    for (int i = 0; i < L0.n; ++i) {
+      int64_t c = 0;
+      for (int64_t k = L0.A.ptr[i]; k < L0.A.ptr[i + 1]; ++k)
+        if (L0.A.col[k] != i) ++c;
+      W.ptr[i + 1] = W.ptr[i] + c;
+    }
+    W.col.reserve(W.ptr[L0.n]);
+    W.val.reserve(W.ptr[L0.n]);
+    for (int i = 0; i < L0.n; ++i)
+      for (int64_t k = L0.A.ptr[i]; k < L0.A.ptr[i + 1]; ++k)
+        if (L0.A.col[k] != i) {
+          W.col.push_back(L0.A.col[k]);
+          W.val.push_back(-L0.A.val[k]);
+        }
+    upload_csr(W, D0.a_ptr, D0.a_col, D0.a_val, D0.A, s);
+    D0.a_diag.upload(L0.s, s);
+    D0.A.diag = D0.a_diag.p;
+    D0.A.avg_row = static_cast<double>(L0.A.nnz()) / L0.n;
+  }
+  for (size_t k = 1; k < h.host.size(); ++k) {
+    const LevelHost& L = h.host[k];
+    LevelDev& D = h.dev[k];
+    upload_csr(L.A, D.a_ptr, D.a_col, D.a_val, D.A, s);
+    upload_csr(L.M, D.m_ptr, D.m_col, D.m_val, D.M, s);
+    upload_csr(L.Psi, D.p_ptr, D.p_col, D.p_val, D.Psi, s);
+    D.h_ptr.upload(L.patch_ptr, s);
+    D.h_mem.upload(L.members, s);
+    D.h_u.upload(L.hh_u, s);
+    D.h_scale.upload(L.hh_scale, s);
+    D.H.npatch = L.n;
+    D.H.nfine = h.host[k - 1].n;
+    D.H.nred = h.host[k - 1].n - L.n;
+    D.H.ptr = D.h_ptr.p;
+    D.H.members = D.h_mem.p;
+    D.H.u = D.h_u.p;
+    D.H.scale = D.h_scale.p;
+  }
+  MMD_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace mmd

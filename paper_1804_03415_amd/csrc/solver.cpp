@@ -1,0 +1,888 @@
+// Level driver of the hierarchical eigensolver on the device.
+//
+// Every length-N operation runs in the kernels of kernels.hip; the host keeps
+// only small dense FP64 objects (the Lanczos matrix T, Ritz and Gram matrices,
+// the coarsest-level operators) and the control flow of Alg. 2-6.  CG / PCG
+// scalars live on the device per column; the host reads the convergence flags
+// once per chunk of iterations, never per iteration.
+#include "solver.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <numeric>
+
+#include "dense.h"
+
+namespace mmd {
+
+namespace {
+
+// Philox4x32-10 (Salmon et al., SC'11); random start vectors of Alg. 3/4.
+void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c[0];
+    const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c[2];
+    const uint32_t hi0 = static_cast<uint32_t>(p0 >> 32), lo0 = static_cast<uint32_t>(p0);
+    const uint32_t hi1 = static_cast<uint32_t>(p1 >> 32), lo1 = static_cast<uint32_t>(p1);
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+// entry i of draw `call` at `level`: counter (i/2, call, level, 0), values in [-0.5, 0.5)
+void uniform_vector(std::vector<double>& v, int n, uint64_t seed, int level, int64_t call) {
+  v.resize(n);
+  const double inv53 = 1.0 / 9007199254740992.0;
+  for (int c = 0; 2 * c < n; ++c) {
+    uint32_t ctr[4] = {static_cast<uint32_t>(c), static_cast<uint32_t>(call),
+                       static_cast<uint32_t>(level), 0u};
+    philox4x32_10(ctr, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
+    const double a = (static_cast<double>(ctr[0] >> 5) * 67108864.0 + static_cast<double>(ctr[1] >> 6)) * inv53;
+    const double b = (static_cast<double>(ctr[2] >> 5) * 67108864.0 + static_cast<double>(ctr[3] >> 6)) * inv53;
+    v[2 * c] = a - 0.5;
+    if (2 * c + 1 < n) v[2 * c + 1] = b - 0.5;
+  }
+}
+
+ColScalars make_scalars(Pool& pool, const std::string& tag, int b) {
+  ColScalars sc;
+  sc.rr = pool.d(tag + ":rr", b);
+  sc.rr2 = pool.d(tag + ":rr2", b);
+  sc.alpha = pool.d(tag + ":al", b);
+  sc.beta = pool.d(tag + ":be", b);
+  sc.bn2 = pool.d(tag + ":bn", b);
+  sc.tol2 = pool.d(tag + ":tol", b);
+  sc.active = pool.i(tag + ":act", b);
+  sc.iters = pool.i(tag + ":it", b);
+  sc.notspd = pool.i(tag + ":spd", 1);
+  return sc;
+}
+
+// Tridiagonal part of the dense Lanczos matrix (fill from restarts is rounding).
+void tri_of(const std::vector<double>& T, int ld, int m, std::vector<double>& d,
+            std::vector<double>& e) {
+  d.resize(m);
+  e.resize(m > 0 ? m - 1 : 0);
+  for (int i = 0; i < m; ++i) d[i] = T[(size_t)i * ld + i];
+  for (int i = 0; i + 1 < m; ++i) e[i] = T[(size_t)(i + 1) * ld + i];
+}
+
+int keep_count(const std::vector<double>& D, int ml, double mu_h, double gamma) {
+  int mh = 0;
+  for (int i = 0; i < ml; ++i)
+    if (D[i] >= mu_h) ++mh;
+  while (mh > 0 && D[ml - 1] > gamma * D[mh - 1]) --mh;
+  return mh;
+}
+
+}  // namespace
+
+struct Solver::Lanczos {
+  int k = 0, n = 0;
+  const double* Vini = nullptr;
+  int mi = 0;
+  double* V = nullptr;
+  double* Vtmp = nullptr;
+  int cap = 0;
+  int j = 0;
+  double* f = nullptr;
+  double* w = nullptr;
+  double* y = nullptr;
+  std::vector<double> T;
+  double beta_f = 0.0;
+  double wnorm = 1.0;
+  double eps_op = 0.0;
+};
+
+Solver::Solver(mmd_handle& h, hipStream_t s, const eig_opts& o, eig_stats* st)
+    : h_(h), s_(s), o_(o), st_(st) {
+  if (o_.alpha <= 0) o_.alpha = 3.0;
+  if (o_.beta <= 0) o_.beta = 1.0;
+  if (o_.restart_mult <= 0) o_.restart_mult = 1;
+  if (o_.max_restarts <= 0) o_.max_restarts = 2000;
+  if (o_.max_refine <= 0) o_.max_refine = 200;
+  hd_.ensure(4096);
+  hi_.ensure(4096);
+}
+
+// ------------------------------------------------------------------ operators
+void Solver::applyA(int k, const double* X, int ldx, double* Y, int ldy, int b) {
+  spmm(h_.dev[k].A, X, ldx, Y, ldy, b, s_);
+}
+
+void Solver::applyM(int k, const double* X, int ldx, double* Y, int ldy, int b) {
+  if (k == 0) copy_block(X, ldx, Y, ldy, nlev(0), b, s_);
+  else spmm(h_.dev[k].M, X, ldx, Y, ldy, b, s_);
+}
+
+void Solver::applyB(int k, const double* X, int ldx, double* Y, int ldy, int b) {
+  // B^(k+1) = U^T A^(k) U on the reduced space of the transfer k -> k+1
+  const HouseView& H = h_.dev[k + 1].H;
+  const int n = nlev(k);
+  double* t1 = pool_.d("B:t1", (size_t)n * b);
+  double* t2 = pool_.d("B:t2", (size_t)n * b);
+  house_u(H, X, ldx, t1, b, b, s_);
+  applyA(k, t1, b, t2, b, b);
+  house_ut(H, t2, b, Y, ldy, b, s_);
+}
+
+// ------------------------------------------------------------------ CG
+void Solver::cg(int k, OpKind op, const double* B, int ldb, double* X, int ldx, int n, int b,
+                double tol, bool use_x0, const int* parent, int fixed_iters,
+                const std::string& tag, std::vector<int>* iters) {
+  if (b == 0 || n == 0) return;
+  ColScalars sc = make_scalars(pool_, tag, b);
+  double* R = pool_.d(tag + ":R", (size_t)n * b);
+  double* P = pool_.d(tag + ":P", (size_t)n * b);
+  double* Q = pool_.d(tag + ":Q", (size_t)n * b);
+  double* p1 = pool_.d(tag + ":p1", (size_t)kRedBlocks * b);
+  double* p2 = pool_.d(tag + ":p2", (size_t)kRedBlocks * b);
+  const CsrView* csr = nullptr;
+  if (op == OpKind::A) csr = &h_.dev[k].A;
+  if (op == OpKind::M) csr = &h_.dev[k].M;
+  auto apply = [&](const double* x, int lx, double* y, int ly) {
+    if (op == OpKind::A) applyA(k, x, lx, y, ly, b);
+    else if (op == OpKind::M) applyM(k, x, lx, y, ly, b);
+    else applyB(k, x, lx, y, ly, b);
+  };
+  if (use_x0) {
+    apply(X, ldx, R, b);
+    rsub(B, ldb, R, b, n, b, s_);
+  } else {
+    copy_block(B, ldb, R, b, n, b, s_);
+    zero_block(X, ldx, n, b, s_);
+  }
+  const int nb = col_dot(B, ldb, B, ldb, n, b, p1, s_);
+  col_dot(R, b, R, b, n, b, p2, s_);
+  cg_init(sc, p1, p2, nb, b, tol, parent, s_);
+  MMD_HIP(hipMemsetAsync(sc.notspd, 0, sizeof(int), s_));
+  auto iterate = [&](bool first) {
+    int np;
+    if (csr) {
+      np = spmm(*csr, R, b, Q, b, b, s_, true, first, sc.beta, P, b, p1);
+    } else {
+      xpay(R, b, P, b, n, b, sc.beta, first, s_);
+      apply(P, b, Q, b);
+      np = col_dot(P, b, Q, b, n, b, p1, s_);
+    }
+    cg_alpha(sc, p1, np, b, s_);
+    const int nu = cg_update(X, ldx, R, P, Q, b, n, b, sc.alpha, p2, s_);
+    cg_beta(sc, p2, nu, b, s_);
+  };
+  if (fixed_iters > 0) {
+    for (int t = 0; t < fixed_iters; ++t) iterate(t == 0);
+    return;
+  }
+  const int maxit = 100000;
+  int done = 0, chunk = 4;
+  bool first = true;
+  while (true) {
+    for (int t = 0; t < chunk; ++t) {
+      iterate(first);
+      first = false;
+    }
+    done += chunk;
+    hi_.ensure(b + 1);
+    d2h(hi_.p, sc.active, b);
+    d2h(hi_.p + b, sc.notspd, 1);
+    sync();
+    MMD_REQUIRE(hi_.p[b] == 0, MMD_ENOTSPD, "CG curvature p^T A p <= 0");
+    bool any = false;
+    for (int c = 0; c < b; ++c) any |= hi_.p[c] != 0;
+    if (!any) break;
+    MMD_REQUIRE(done < maxit, MMD_ENOCONV, "CG reached the iteration cap");
+    chunk = std::min(chunk * 2, 64);
+  }
+  if (iters) {
+    iters->resize(b);
+    d2h(hi_.p, sc.iters, b);
+    sync();
+    std::copy(hi_.p, hi_.p + b, iters->begin());
+  }
+}
+
+void Solver::pcg(int k, const double* B, int ldb, double* X, int ldx, int b, double tol,
+                 bool use_x0, std::vector<int>* iters) {
+  const int n = nlev(k);
+  if (k == 0) {
+    cg(0, OpKind::A, B, ldb, X, ldx, n, b, tol, use_x0, nullptr, 0, "cg0", iters);
+    return;
+  }
+  if (b == 0) return;
+  const std::string tag = "pcg";
+  ColScalars sc = make_scalars(pool_, tag, b);
+  double* R = pool_.d(tag + ":R", (size_t)n * b);
+  double* Z = pool_.d(tag + ":Z", (size_t)n * b);
+  double* Zo = pool_.d(tag + ":Zo", (size_t)n * b);
+  double* P = pool_.d(tag + ":P", (size_t)n * b);
+  double* Q = pool_.d(tag + ":Q", (size_t)n * b);
+  double* p1 = pool_.d(tag + ":p1", (size_t)kRedBlocks * b);
+  double* p2 = pool_.d(tag + ":p2", (size_t)kRedBlocks * b);
+  double* p3 = pool_.d(tag + ":p3", (size_t)kRedBlocks * b);
+  if (use_x0) {
+    applyA(k, X, ldx, R, b, b);
+    rsub(B, ldb, R, b, n, b, s_);
+  } else {
+    copy_block(B, ldb, R, b, n, b, s_);
+    zero_block(X, ldx, n, b, s_);
+  }
+  const int nb = col_dot(B, ldb, B, ldb, n, b, p1, s_);
+  col_dot(R, b, R, b, n, b, p2, s_);
+  cg_init(sc, p1, p2, nb, b, tol, nullptr, s_);
+  MMD_HIP(hipMemsetAsync(sc.notspd, 0, sizeof(int), s_));
+  const double tol_in = 0.1 * tol;
+  auto minv = [&](double* Zout) {
+    cg(k, OpKind::M, R, b, Zout, b, n, b, tol_in, false, sc.active, inner_iters_, "inner", nullptr);
+  };
+  minv(Z);
+  {
+    const int nz = col_dot(R, b, Z, b, n, b, p1, s_);
+    reduce_partials(p1, nz, b, sc.rr, s_);  // rz
+  }
+  const int maxit = 100000;
+  int done = 0, chunk = 4;
+  bool first = true;
+  int64_t inner_total = 0;
+  while (true) {
+    for (int t = 0; t < chunk; ++t) {
+      const int np = spmm(h_.dev[k].A, Z, b, Q, b, b, s_, true, first, sc.beta, P, b, p1);
+      cg_alpha(sc, p1, np, b, s_);
+      const int nu = cg_update(X, ldx, R, P, Q, b, n, b, sc.alpha, p2, s_);
+      pcg_conv(sc, p2, nu, b, s_);
+      std::swap(Z, Zo);
+      minv(Z);
+      const int nd = col_dot2(R, b, Z, Zo, b, n, b, p1, p3, s_);
+      pcg_beta(sc, p1, p3, nd, b, s_);
+      first = false;
+    }
+    done += chunk;
+    inner_total += chunk;
+    hi_.ensure(2 * b + 2);
+    d2h(hi_.p, sc.active, b);
+    d2h(hi_.p + b, sc.notspd, 1);
+    d2h(hi_.p + b + 1, pool_.i("inner:act", b), b);
+    sync();
+    MMD_REQUIRE(hi_.p[b] == 0, MMD_ENOTSPD, "PCG curvature p^T A p <= 0");
+    bool any = false, inner_open = false;
+    for (int c = 0; c < b; ++c) {
+      any |= hi_.p[c] != 0;
+      inner_open |= hi_.p[b + 1 + c] != 0;
+    }
+    if (inner_open && inner_iters_ < 64) inner_iters_ += 4;
+    if (!any) break;
+    MMD_REQUIRE(done < maxit, MMD_ENOCONV, "PCG reached the iteration cap");
+    chunk = std::min(chunk * 2, 32);
+  }
+  if (st_) st_->cg_M_iters[k] += inner_total * inner_iters_ * b;
+  if (iters) {
+    iters->resize(b);
+    d2h(hi_.p, sc.iters, b);
+    sync();
+    std::copy(hi_.p, hi_.p + b, iters->begin());
+  }
+}
+
+// ------------------------------------------------------------------ Lanczos (Alg. 3)
+double Solver::mnorm2(int k, const double* x) {
+  const int n = nlev(k);
+  double* p = pool_.d("mn:p", kRedBlocks);
+  double* out = pool_.d("mn:o", 1);
+  int nb;
+  if (k == 0) {
+    nb = col_dot(x, 1, x, 1, n, 1, p, s_);
+  } else {
+    double* y = pool_.d("mn:y", n);
+    applyM(k, x, 1, y, 1, 1);
+    nb = col_dot(x, 1, y, 1, n, 1, p, s_);
+  }
+  reduce_partials(p, nb, 1, out, s_);
+  d2h(hd_.p, out, 1);
+  sync();
+  return hd_.p[0];
+}
+
+void Solver::lanczos_orth(Lanczos& L, double* w, int jcols, std::vector<double>* hlast) {
+  const int n = L.n;
+  double* y = L.y;
+  double* h1 = pool_.d("lz:h1", std::max(L.mi, 1));
+  double* h2 = pool_.d("lz:h2", std::max(jcols, 1));
+  double* work = pool_.d("lz:gw", (size_t)256 * std::max(std::max(L.mi, jcols), 1));
+  double last = 0.0;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (L.k == 0) copy_block(w, 1, y, 1, n, 1, s_);
+    else applyM(L.k, w, 1, y, 1, 1);
+    if (L.mi > 0) {
+      gemv_t(L.Vini, L.mi, y, n, L.mi, h1, work, s_);
+      gemv_n_sub(L.Vini, L.mi, h1, n, L.mi, w, s_);
+    }
+    if (jcols > 0) {
+      gemv_t(L.V, L.cap, y, n, jcols, h2, work, s_);
+      gemv_n_sub(L.V, L.cap, h2, n, jcols, w, s_);
+      if (hlast) {
+        d2h(hd_.p + pass, h2 + jcols - 1, 1);
+      }
+    }
+  }
+  if (hlast && jcols > 0) {
+    sync();
+    last = hd_.p[0] + hd_.p[1];
+    hlast->assign(1, last);
+  }
+}
+
+void Solver::lanczos_random(Lanczos& L, double* out) {
+  std::vector<double> v;
+  uniform_vector(v, L.n, o_.seed, L.k, draws_[L.k]++);
+  h2d(out, v.data(), L.n);
+  lanczos_orth(L, out, L.j, nullptr);
+  sync();  // v goes out of scope
+}
+
+void Solver::lanczos_init(Lanczos& L, int k, const double* Vini, int mi, int cap_cols) {
+  L.k = k;
+  L.n = nlev(k);
+  L.Vini = Vini;
+  L.mi = mi;
+  L.cap = std::max(cap_cols, 1);
+  L.j = 0;
+  L.V = pool_.d("lz:V", (size_t)L.n * L.cap);
+  L.Vtmp = pool_.d("lz:Vt", (size_t)L.n * L.cap);
+  L.f = pool_.d("lz:f", L.n);
+  L.w = pool_.d("lz:w", L.n);
+  L.y = pool_.d("lz:y", L.n);
+  L.T.assign((size_t)L.cap * L.cap, 0.0);
+  L.wnorm = 1.0;
+  lanczos_random(L, L.f);
+  L.beta_f = std::sqrt(mnorm2(k, L.f));
+}
+
+void Solver::lanczos_steps(Lanczos& L, int nsteps) {
+  const int n = L.n;
+  double* v = pool_.d("lz:v", n);
+  double* rhs = pool_.d("lz:rhs", n);
+  for (int t = 0; t < nsteps; ++t) {
+    const int j = L.j;
+    MMD_REQUIRE(j < L.cap, MMD_EINVAL, "Lanczos basis capacity exceeded");
+    double coupling;
+    if (j > 0 && L.beta_f <= 1e-12 * L.wnorm) {
+      lanczos_random(L, L.f);
+      const double b2 = std::sqrt(mnorm2(L.k, L.f));
+      axpby(1.0 / b2, L.f, 1, 0.0, v, 1, n, 1, s_);
+      coupling = 0.0;
+    } else {
+      axpby(1.0 / L.beta_f, L.f, 1, 0.0, v, 1, n, 1, s_);
+      coupling = L.beta_f;
+    }
+    copy_block(v, 1, L.V + j, L.cap, n, 1, s_);
+    if (j > 0) {
+      L.T[(size_t)j * L.cap + j - 1] = coupling;
+      L.T[(size_t)(j - 1) * L.cap + j] = coupling;
+    }
+    // w = OP(v) = pcg(A, M v, M, 0, eps)
+    if (L.k == 0) copy_block(v, 1, rhs, 1, n, 1, s_);
+    else applyM(L.k, v, 1, rhs, 1, 1);
+    std::vector<int> it;
+    pcg(L.k, rhs, 1, L.w, 1, 1, L.eps_op, false, st_ ? &it : nullptr);
+    if (st_) {
+      st_->pcg_A_calls[L.k] += 1;
+      st_->pcg_A_iters[L.k] += it.empty() ? 0 : it[0];
+    }
+    L.wnorm = std::sqrt(mnorm2(L.k, L.w));
+    std::vector<double> hl;
+    lanczos_orth(L, L.w, j + 1, &hl);
+    L.T[(size_t)j * L.cap + j] = hl[0];
+    std::swap(L.f, L.w);
+    L.beta_f = std::sqrt(mnorm2(L.k, L.f));
+    L.j = j + 1;
+    if (st_) st_->lanczos_steps[L.k] += 1;
+  }
+}
+
+bool Solver::ritz_converged(Lanczos& L, int nwant, double eps, bool relative) {
+  const int m = L.j;
+  std::vector<double> d, e, w;
+  tri_of(L.T, L.cap, m, d, e);
+  std::vector<double> last(m, 0.0);
+  last[m - 1] = 1.0;
+  dense::tridiag_eig(m, d.data(), e.data(), w, last.data(), 1);
+  for (int q = 0; q < nwant; ++q) {
+    const int i = m - 1 - q;  // largest first
+    const double res = L.beta_f * std::fabs(last[i]);
+    const double lim = relative ? eps * std::fabs(w[i]) : eps;
+    if (!(res <= lim)) return false;
+  }
+  return true;
+}
+
+void Solver::restart(Lanczos& L, int kkeep, int p) {
+  const int m = L.j;
+  MMD_REQUIRE(m == kkeep + p, MMD_EINVAL, "restart size mismatch");
+  std::vector<double> T((size_t)m * m);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) T[(size_t)i * m + j] = L.T[(size_t)i * L.cap + j];
+  std::vector<double> d, e, theta;
+  tri_of(L.T, L.cap, m, d, e);
+  dense::tridiag_eig(m, d.data(), e.data(), theta, nullptr, 0);
+  std::vector<double> Q((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i) Q[(size_t)i * m + i] = 1.0;
+  for (int q = 0; q < p; ++q) dense::shifted_qr_step(m, T.data(), theta[q], Q.data());
+  const double bk = T[(size_t)kkeep * m + kkeep - 1];
+  const double sk = Q[(size_t)(m - 1) * m + kkeep - 1];
+  // f <- V Q(:, k+1) T(k+1, k) + f Q(m, k)   (with the basis before truncation)
+  std::vector<double> g(m), qk((size_t)m * kkeep);
+  for (int i = 0; i < m; ++i) g[i] = -Q[(size_t)i * m + kkeep] * bk;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < kkeep; ++j) qk[(size_t)i * kkeep + j] = Q[(size_t)i * m + j];
+  double* gd = pool_.d("rs:g", m);
+  double* qd = pool_.d("rs:q", (size_t)m * kkeep);
+  h2d(gd, g.data(), m);
+  h2d(qd, qk.data(), (size_t)m * kkeep);
+  axpby(sk, L.f, 1, 0.0, L.f, 1, L.n, 1, s_);
+  gemv_n_sub(L.V, L.cap, gd, L.n, m, L.f, s_);
+  gemm_nn(L.V, L.cap, qd, kkeep, L.Vtmp, L.cap, L.n, m, kkeep, 1.0, 0.0, s_);
+  std::swap(L.V, L.Vtmp);
+  std::vector<double> Tn((size_t)L.cap * L.cap, 0.0);
+  for (int i = 0; i < kkeep; ++i)
+    for (int j = 0; j < kkeep; ++j) Tn[(size_t)i * L.cap + j] = T[(size_t)i * m + j];
+  L.T.swap(Tn);
+  L.j = kkeep;
+  L.beta_f = std::sqrt(mnorm2(L.k, L.f));  // also waits for the host arrays above
+  if (st_) st_->restarts[L.k] += 1;
+}
+
+// ------------------------------------------------------------------ extension (Alg. 4)
+void Solver::extend(int k, double*& V, std::vector<double>& D, int& m, int m_tar, double eps,
+                    double mu_ex, int d, bool relative) {
+  const int n = nlev(k);
+  const int mi = m;
+  if (st_) st_->ext_in[k] += mi;
+  const int want = m_tar - mi;
+  const int cap = n - mi;
+  if (want <= 0 || cap <= 0) {
+    if (st_) st_->ext_out[k] += mi;
+    return;
+  }
+  const int c = o_.restart_mult;
+  const int vcap = std::min(cap, want + c * std::max(want, d));
+  Lanczos L;
+  L.eps_op = eps;
+  lanczos_init(L, k, V, mi, vcap);
+  int kcur = 0, restarts = 0;
+  auto converge = [&](int kk, int p) {
+    while (!ritz_converged(L, kk, eps, relative)) {
+      if (p <= 0) break;
+      lanczos_steps(L, p);
+      restart(L, kk, p);
+      MMD_REQUIRE(++restarts <= o_.max_restarts, MMD_ENOCONV, "extension: restart cap reached");
+    }
+  };
+  while (true) {
+    const int kk = std::min(std::min(kcur + d, want), cap);
+    const int p = std::min(c * d, cap - kk);
+    lanczos_steps(L, kk - L.j);
+    converge(kk, p);
+    kcur = kk;
+    std::vector<double> dd, ee, th;
+    tri_of(L.T, L.cap, L.j, dd, ee);
+    dense::tridiag_eig(L.j, dd.data(), ee.data(), th, nullptr, 0);
+    const double mu_hat = th[std::min(d, kcur) - 1];
+    if (mu_hat < mu_ex || kcur >= want || kcur >= cap) break;
+  }
+  const int mnew = kcur;
+  converge(mnew, std::min(c * mnew, cap - mnew));
+  // Schur (symmetric eig) of T, descending
+  std::vector<double> T((size_t)mnew * mnew);
+  for (int i = 0; i < mnew; ++i)
+    for (int j = 0; j < mnew; ++j) T[(size_t)i * mnew + j] = L.T[(size_t)i * L.cap + j];
+  std::vector<double> w, Z;
+  dense::sym_eig(mnew, T.data(), w, &Z);
+  std::vector<double> Y((size_t)mnew * mnew);
+  for (int i = 0; i < mnew; ++i)
+    for (int j = 0; j < mnew; ++j) Y[(size_t)i * mnew + j] = Z[(size_t)i * mnew + (mnew - 1 - j)];
+  double* Yd = pool_.d("ex:Y", (size_t)mnew * mnew);
+  h2d(Yd, Y.data(), Y.size());
+  const int mo = mi + mnew;
+  double* Vn = pool_.d(V == pool_.d("VA", 0) ? "VB" : "VA", (size_t)n * mo);
+  double* tmp = pool_.d("ex:tmp", (size_t)n * mo);
+  copy_block(V, mi, tmp, mo, n, mi, s_);
+  gemm_nn(L.V, L.cap, Yd, mnew, tmp + mi, mo, n, mnew, mnew, 1.0, 0.0, s_);
+  std::vector<double> Dn(D.begin(), D.begin() + mi);
+  for (int j = 0; j < mnew; ++j) Dn.push_back(w[mnew - 1 - j]);
+  std::vector<int> order(mo);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return Dn[a] > Dn[b]; });
+  int* od = pool_.i("ex:ord", mo);
+  h2d(od, order.data(), mo);
+  gather_cols(tmp, mo, od, Vn, mo, n, mo, s_);
+  D.resize(mo);
+  for (int j = 0; j < mo; ++j) D[j] = Dn[order[j]];
+  sync();
+  V = Vn;
+  m = mo;
+  if (st_) st_->ext_out[k] += mo;
+}
+
+void Solver::multiplicity_check(double*& V, std::vector<double>& D, int m, double eps, int d) {
+  const int n = nlev(0);
+  const int cap = n - m;
+  if (cap <= 0 || m == 0) return;
+  const int c = o_.restart_mult;
+  for (int swaps = 0; swaps < 64; ++swaps) {
+    const int s = std::min(d + 10, cap);
+    const int p = std::min(c * d, cap - 1);
+    Lanczos L;
+    L.eps_op = eps;
+    lanczos_init(L, 0, V, m, std::max(s, 1 + p));
+    lanczos_steps(L, s);
+    std::vector<double> dd, ee, th;
+    tri_of(L.T, L.cap, L.j, dd, ee);
+    dense::tridiag_eig(L.j, dd.data(), ee.data(), th, nullptr, 0);
+    const double lim = D[m - 1] * (1.0 + eps);
+    if (th.back() <= lim) return;
+    while (p > 0 && !ritz_converged(L, 1, eps, true)) {
+      restart(L, 1, L.j - 1);
+      lanczos_steps(L, p);
+    }
+    const int mm = L.j;
+    std::vector<double> T((size_t)mm * mm), w, Z;
+    for (int i = 0; i < mm; ++i)
+      for (int j = 0; j < mm; ++j) T[(size_t)i * mm + j] = L.T[(size_t)i * L.cap + j];
+    dense::sym_eig(mm, T.data(), w, &Z);
+    std::vector<double> y(mm);
+    for (int i = 0; i < mm; ++i) y[i] = Z[(size_t)i * mm + (mm - 1)];
+    double* yd = pool_.d("mc:y", mm);
+    h2d(yd, y.data(), mm);
+    double* u = pool_.d("mc:u", n);
+    gemm_nn(L.V, L.cap, yd, 1, u, 1, n, mm, 1, 1.0, 0.0, s_);
+    copy_block(u, 1, V + (m - 1), m, n, 1, s_);
+    D[m - 1] = w[mm - 1];
+    std::vector<int> order(m);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return D[a] > D[b]; });
+    int* od = pool_.i("mc:ord", m);
+    h2d(od, order.data(), m);
+    double* tmp = pool_.d("mc:tmp", (size_t)n * m);
+    copy_block(V, m, tmp, m, n, m, s_);
+    gather_cols(tmp, m, od, V, m, n, m, s_);
+    std::vector<double> Dn(m);
+    for (int j = 0; j < m; ++j) Dn[j] = D[order[j]];
+    D.swap(Dn);
+    sync();
+    if (st_) st_->missed_swaps += 1;
+  }
+  throw Error(MMD_ENOCONV, "multiplicity check: too many swaps");
+}
+
+// ------------------------------------------------------------------ refinement (Alg. 5)
+void Solver::mqr(int k, double* F, int n, int b, const std::string& tag) {
+  double* MF = pool_.d(tag + ":MF", (size_t)n * b);
+  double* G = pool_.d(tag + ":G", (size_t)b * b);
+  double* Rd = pool_.d(tag + ":R", (size_t)b * b);
+  double* T = pool_.d(tag + ":T", (size_t)n * b);
+  double* work = pool_.d("gram:w", gram_work_size(n, b, b));
+  std::vector<double> Gh((size_t)b * b), R, Ri;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (k == 0) gram(F, b, F, b, n, b, b, G, b, work, s_);
+    else {
+      applyM(k, F, b, MF, b, b);
+      gram(F, b, MF, b, n, b, b, G, b, work, s_);
+    }
+    d2h(Gh.data(), G, Gh.size());
+    sync();
+    MMD_REQUIRE(dense::cholesky_upper(b, Gh.data(), R), MMD_ENOCONV,
+                "M-orthogonal QR: Gram matrix not positive definite");
+    dense::upper_inverse(b, R.data(), Ri);
+    h2d(Rd, Ri.data(), Ri.size());
+    gemm_nn(F, b, Rd, b, T, b, n, b, b, 1.0, 0.0, s_);
+    copy_block(T, b, F, b, n, b, s_);
+    sync();
+  }
+}
+
+void Solver::refine(int k, double*& V, std::vector<double>& D, int& m, double eps, double mu_h,
+                    double lam_max_M, double gamma) {
+  const int ml = m;
+  if (st_) st_->ref_in[k] += ml;
+  if (ml == 0) return;
+  const int n = nlev(k);
+  const HouseView& H = h_.dev[k + 1].H;
+  const int nred = H.nred;
+  double* MQ = pool_.d("rf:MQ", (size_t)n * ml);
+  double* RB = pool_.d("rf:RB", (size_t)std::max(nred, 1) * ml);
+  double* G = pool_.d("rf:G", (size_t)std::max(nred, 1) * ml);
+  double* F = pool_.d("rf:F", (size_t)n * ml);
+  double* F2 = pool_.d("rf:F2", (size_t)n * ml);
+  double* Q = pool_.d("rf:Q", (size_t)n * ml);
+  double* W = pool_.d("rf:W", (size_t)n * ml);
+  double* Tm = pool_.d("rf:T", (size_t)n * ml);
+  double* Qp = pool_.d("rf:Qp", (size_t)n * ml);
+  double* E = pool_.d("rf:E", (size_t)n * ml);
+  double* Dd = pool_.d("rf:D", ml);
+  double* Pd = pool_.d("rf:P", (size_t)ml * ml);
+  double* Sd = pool_.d("rf:S", (size_t)ml * ml);
+  double* work = pool_.d("gram:w", gram_work_size(n, ml, ml));
+  // start block F = Q D + U G, g_i = cg(B, U^T M q_i, 0, eps)
+  applyM(k, V, ml, MQ, ml, ml);
+  if (nred > 0) {
+    house_ut(H, MQ, ml, RB, ml, ml, s_);
+    std::vector<int> it;
+    cg(k, OpKind::B, RB, ml, G, ml, nred, ml, eps, false, nullptr, 0, "bcg", st_ ? &it : nullptr);
+    if (st_) {
+      st_->cg_B_calls[k] += ml;
+      for (int x : it) st_->cg_B_iters[k] += x;
+    }
+    house_u(H, G, ml, F, ml, ml, s_);
+  } else {
+    zero_block(F, ml, n, ml, s_);
+  }
+  h2d(Dd, D.data(), ml);
+  scale_cols(V, ml, Dd, F, ml, n, ml, true, s_);
+  std::vector<double> mu_prev(D.begin(), D.begin() + ml), Dn(ml);
+  bool have_prev = false;
+  int mh = 0;
+  const double thresh = eps / std::sqrt(lam_max_M);
+  std::vector<double> Sh((size_t)ml * ml), w, Z, Ph((size_t)ml * ml);
+  int it = 0;
+  for (it = 1; it <= o_.max_refine; ++it) {
+    mqr(k, F, n, ml, "rq");
+    copy_block(F, ml, Q, ml, n, ml, s_);
+    applyM(k, Q, ml, W, ml, ml);
+    h2d(Dd, mu_prev.data(), ml);
+    scale_cols(Q, ml, Dd, F2, ml, n, ml, false, s_);
+    std::vector<int> its;
+    pcg(k, W, ml, F2, ml, ml, eps, true, st_ ? &its : nullptr);
+    if (st_) {
+      st_->pcg_A_calls[k] += ml;
+      for (int x : its) st_->pcg_A_iters[k] += x;
+    }
+    gram(W, ml, F2, ml, n, ml, ml, Sd, ml, work, s_);
+    d2h(Sh.data(), Sd, Sh.size());
+    sync();
+    dense::sym_eig(ml, Sh.data(), w, &Z);
+    for (int j = 0; j < ml; ++j) {
+      Dn[j] = w[ml - 1 - j];
+      for (int i = 0; i < ml; ++i) Ph[(size_t)i * ml + j] = Z[(size_t)i * ml + (ml - 1 - j)];
+    }
+    mh = keep_count(Dn, ml, mu_h, gamma);
+    h2d(Pd, Ph.data(), Ph.size());
+    gemm_nn(Q, ml, Pd, ml, Tm, ml, n, ml, ml, 1.0, 0.0, s_);
+    std::swap(Q, Tm);
+    gemm_nn(F2, ml, Pd, ml, Tm, ml, n, ml, ml, 1.0, 0.0, s_);
+    std::swap(F2, Tm);
+    if (st_) st_->ref_iter[k] += 1;
+    bool done = false;
+    if (have_prev && mh > 0) {
+      applyM(k, Q, ml, MQ, ml, ml);
+      double* X = pool_.d("rf:X", (size_t)mh * mh);
+      double* wk = pool_.d("gram:w2", gram_work_size(n, mh, mh));
+      gram(Qp, ml, MQ, ml, n, mh, mh, X, mh, wk, s_);
+      copy_block(Q, ml, E, mh, n, mh, s_);
+      gemm_nn(Qp, ml, X, mh, E, mh, n, mh, mh, -1.0, 1.0, s_);
+      double* pr = pool_.d("rf:pr", (size_t)kRedBlocks * mh);
+      double* cn = pool_.d("rf:cn", mh);
+      const int nb = col_dot(E, mh, E, mh, n, mh, pr, s_);
+      reduce_partials(pr, nb, mh, cn, s_);
+      std::vector<double> cnh(mh);
+      d2h(cnh.data(), cn, mh);
+      sync();
+      double fro = 0.0;
+      for (double x : cnh) fro += x;
+      done = std::sqrt(fro) < thresh;
+    } else if (have_prev && mh == 0) {
+      done = true;
+    }
+    copy_block(Q, ml, Qp, ml, n, ml, s_);
+    have_prev = true;
+    mu_prev = Dn;
+    std::swap(F, F2);
+    if (done) break;
+  }
+  MMD_REQUIRE(it <= o_.max_refine, MMD_ENOCONV, "refinement: iteration cap reached");
+  double* Vo = pool_.d(V == pool_.d("VA", 0) ? "VB" : "VA", (size_t)n * std::max(mh, 1));
+  copy_block(Q, ml, Vo, mh, n, mh, s_);
+  sync();
+  V = Vo;
+  m = mh;
+  D.assign(Dn.begin(), Dn.begin() + mh);
+  if (st_) st_->ref_out[k] += mh;
+}
+
+// ------------------------------------------------------------------ output step
+void Solver::final_pairs(double* V, const std::vector<double>& D, int m, int nev, double tol,
+                         double* evals, double* evecs) {
+  const int n = nlev(0);
+  MMD_REQUIRE(m >= nev, MMD_ENOCONV, "fewer converged pairs than requested");
+  double* F = pool_.d("fp:F", (size_t)n * m);
+  double* Dd = pool_.d("fp:D", m);
+  double* AQ = pool_.d("fp:AQ", (size_t)n * m);
+  double* Hd = pool_.d("fp:H", (size_t)m * m);
+  double* Yd = pool_.d("fp:Y", (size_t)m * nev);
+  double* Vo = pool_.d("fp:V", (size_t)n * nev);
+  double* work = pool_.d("gram:w", gram_work_size(n, m, m));
+  h2d(Dd, D.data(), m);
+  scale_cols(V, m, Dd, F, m, n, m, false, s_);
+  std::vector<int> its;
+  cg(0, OpKind::A, V, m, F, m, n, m, tol, true, nullptr, 0, "cg0", st_ ? &its : nullptr);
+  if (st_) {
+    st_->pcg_A_calls[0] += m;
+    for (int x : its) st_->pcg_A_iters[0] += x;
+  }
+  mqr(0, F, n, m, "fq");
+  applyA(0, F, m, AQ, m, m);
+  gram(F, m, AQ, m, n, m, m, Hd, m, work, s_);
+  std::vector<double> Hh((size_t)m * m), lam, Z;
+  d2h(Hh.data(), Hd, Hh.size());
+  sync();
+  dense::sym_eig(m, Hh.data(), lam, &Z);
+  std::vector<double> Yh((size_t)m * nev);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < nev; ++j) Yh[(size_t)i * nev + j] = Z[(size_t)i * m + j];
+  h2d(Yd, Yh.data(), Yh.size());
+  gemm_nn(F, m, Yd, nev, Vo, nev, n, m, nev, 1.0, 0.0, s_);
+  double* pr = pool_.d("fp:pr", (size_t)kRedBlocks * nev);
+  double* cn = pool_.d("fp:cn", nev);
+  int* ai = pool_.i("fp:ai", nev);
+  double* av = pool_.d("fp:av", nev);
+  const int nb = col_dot(Vo, nev, Vo, nev, n, nev, pr, s_);
+  reduce_partials(pr, nb, nev, cn, s_);
+  col_absmax(Vo, nev, n, nev, ai, av, s_);
+  std::vector<double> nrm(nev), amax(nev), scale(nev);
+  d2h(nrm.data(), cn, nev);
+  d2h(amax.data(), av, nev);
+  sync();
+  for (int j = 0; j < nev; ++j) scale[j] = (amax[j] < 0 ? -1.0 : 1.0) / std::sqrt(nrm[j]);
+  double* sd = pool_.d("fp:sc", nev);
+  h2d(sd, scale.data(), nev);
+  to_colmajor(Vo, nev, sd, evecs, n, nev, s_);
+  for (int j = 0; j < nev; ++j) evals[j] = lam[j];
+  sync();
+}
+
+// ------------------------------------------------------------------ driver (Alg. 6)
+void Solver::leftmost(int nev, double tol, double* evals, double* evecs) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const int K = h_.K;
+  const int n0 = nlev(0);
+  MMD_REQUIRE(nev > 0 && nev <= n0, MMD_EINVAL, "nev out of range");
+  MMD_REQUIRE(tol > 0 && tol < 1, MMD_EINVAL, "tol must be in (0, 1)");
+  const double alpha = o_.alpha, beta = o_.beta, gamma = (1.0 + beta) / alpha;
+  std::vector<double> eps_op(K + 1), mu_re(K + 1), mu_ex(K + 1);
+  std::vector<int> dd(K + 1);
+  for (int k = 0; k <= K; ++k) {
+    eps_op[k] = k == 0 ? tol : 0.1 * h_.eps[k];
+    mu_re[k] = k + 1 <= K ? alpha * h_.eps[k + 1] : 0.0;
+    mu_ex[k] = beta * h_.eps[k];
+    dd[k] = std::max(1, std::min(nlev(k) / 10, nev / 10));
+  }
+  if (st_) {
+    std::memset(st_, 0, sizeof(eig_stats));
+    st_->K = K;
+  }
+  double* V = pool_.d("VA", 1);
+  std::vector<double> D;
+  int m = 0;
+  if (K > 0) {
+    // Alg. 6 first step: coarsest generalised eigenproblem (dense, host)
+    const LevelHost& L = h_.host[K];
+    const int nk = L.n;
+    std::vector<double> A((size_t)nk * nk, 0.0), M((size_t)nk * nk, 0.0);
+    for (int i = 0; i < nk; ++i) {
+      for (int64_t q = L.A.ptr[i]; q < L.A.ptr[i + 1]; ++q) A[(size_t)i * nk + L.A.col[q]] = L.A.val[q];
+      for (int64_t q = L.M.ptr[i]; q < L.M.ptr[i + 1]; ++q) M[(size_t)i * nk + L.M.col[q]] = L.M.val[q];
+    }
+    std::vector<double> lam, Z;
+    MMD_REQUIRE(dense::gen_eig(nk, A.data(), M.data(), lam, Z), MMD_ENOTSPD,
+                "coarsest M not positive definite");
+    int keep = 0;
+    for (int i = 0; i < nk; ++i)
+      if (1.0 / lam[i] >= mu_ex[K]) ++keep;
+    keep = std::min(keep, nev);
+    std::vector<double> Zk((size_t)nk * std::max(keep, 1));
+    for (int i = 0; i < nk; ++i)
+      for (int j = 0; j < keep; ++j) Zk[(size_t)i * keep + j] = Z[(size_t)i * nk + j];
+    V = pool_.d("VA", (size_t)nk * std::max(keep, 1));
+    h2d(V, Zk.data(), (size_t)nk * keep);
+    D.resize(keep);
+    for (int j = 0; j < keep; ++j) D[j] = 1.0 / lam[j];
+    m = keep;
+    sync();
+    if (st_) st_->ext_out[K] = keep;
+  }
+  for (int k = K - 1; k >= 0; --k) {
+    const auto tl = std::chrono::steady_clock::now();
+    cur_level_ = k;
+    // reform V <- Psi^(k+1) V
+    const int nk = nlev(k);
+    double* Vn = pool_.d(V == pool_.d("VA", 0) ? "VB" : "VA", (size_t)nk * std::max(m, 1));
+    if (m > 0) spmm(h_.dev[k + 1].Psi, V, m, Vn, m, m, s_);
+    V = Vn;
+    refine(k, V, D, m, eps_op[k], mu_re[k], h_.host[k].lam_max_M, gamma);
+    extend(k, V, D, m, nev, eps_op[k], mu_ex[k], dd[k], k == 0);
+    if (st_) st_->seconds_level[k] = std::chrono::duration<double>(std::chrono::steady_clock::now() - tl).count();
+  }
+  if (K == 0) extend(0, V, D, m, nev, tol, 0.0, dd[0], true);
+  multiplicity_check(V, D, m, tol, dd[0]);
+  final_pairs(V, D, m, nev, tol, evals, evecs);
+  if (st_) {
+    st_->nconv = nev;
+    st_->seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+}
+
+// ------------------------------------------------------------------ exposed blocks
+void Solver::apply_op(int level, int op, const double* X, double* Y, int b) {
+  MMD_REQUIRE(level >= 0 && level <= h_.K, MMD_EINVAL, "level out of range");
+  MMD_REQUIRE(b > 0, MMD_EINVAL, "b must be positive");
+  switch (op) {
+    case 0: applyA(level, X, b, Y, b, b); break;
+    case 1: applyM(level, X, b, Y, b, b); break;
+    case 2:
+      MMD_REQUIRE(level < h_.K, MMD_EINVAL, "B needs a coarser level");
+      applyB(level, X, b, Y, b, b);
+      break;
+    case 3:
+      MMD_REQUIRE(level < h_.K, MMD_EINVAL, "U needs a coarser level");
+      house_u(h_.dev[level + 1].H, X, b, Y, b, b, s_);
+      break;
+    case 4:
+      MMD_REQUIRE(level < h_.K, MMD_EINVAL, "U^T needs a coarser level");
+      house_ut(h_.dev[level + 1].H, X, b, Y, b, b, s_);
+      break;
+    case 5:
+      MMD_REQUIRE(level < h_.K, MMD_EINVAL, "Psi needs a coarser level");
+      spmm(h_.dev[level + 1].Psi, X, b, Y, b, b, s_);
+      break;
+    default: throw Error(MMD_EINVAL, "unknown operator");
+  }
+}
+
+void Solver::solve(int level, int kind, const double* rhs, double* X, int b, bool use_x0,
+                   double tol, int* iters_out) {
+  MMD_REQUIRE(level >= 0 && level <= h_.K, MMD_EINVAL, "level out of range");
+  MMD_REQUIRE(b > 0, MMD_EINVAL, "b must be positive");
+  MMD_REQUIRE(tol > 0 && tol < 1, MMD_EINVAL, "tol must be in (0, 1)");
+  std::vector<int> it;
+  if (kind == 0) {
+    pcg(level, rhs, b, X, b, b, tol, use_x0, &it);
+  } else if (kind == 1) {
+    MMD_REQUIRE(level < h_.K, MMD_EINVAL, "B needs a coarser level");
+    const int nred = h_.dev[level + 1].H.nred;
+    cg(level, OpKind::B, rhs, b, X, b, nred, b, tol, use_x0, nullptr, 0, "bcg", &it);
+  } else {
+    throw Error(MMD_EINVAL, "unknown solve kind");
+  }
+  sync();
+  if (iters_out) std::copy(it.begin(), it.end(), iters_out);
+}
+
+}  // namespace mmd

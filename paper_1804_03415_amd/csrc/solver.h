@@ -1,0 +1,99 @@
+// The level driver of the hierarchical eigensolver (Alg. 2-6) on the device.
+#pragma once
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "handle.h"
+
+namespace mmd {
+
+// Device scratch owned by one solver call, reused across phases by name.
+class Pool {
+ public:
+  double* d(const std::string& name, size_t count) { return dbl_[name].ensure(count), dbl_[name].p; }
+  int* i(const std::string& name, size_t count) { return int_[name].ensure(count), int_[name].p; }
+
+ private:
+  std::map<std::string, DBuf<double>> dbl_;
+  std::map<std::string, DBuf<int>> int_;
+};
+
+struct SolveResult {
+  std::vector<int> iters;
+};
+
+class Solver {
+ public:
+  Solver(mmd_handle& h, hipStream_t s, const eig_opts& o, eig_stats* st);
+
+  // eig_leftmost: evals ascending (host), evecs column-major n x nev (device)
+  void leftmost(int nev, double tol, double* evals, double* evecs);
+
+  // building blocks exposed through mmd_apply / mmd_solve
+  void apply_op(int level, int op, const double* X, double* Y, int b);
+  void solve(int level, int kind, const double* rhs, double* X, int b, bool use_x0, double tol,
+             int* iters_out);
+
+ private:
+  struct Block {  // row-major device block n x b (ld = b)
+    double* p = nullptr;
+    int n = 0, b = 0;
+  };
+
+  // level operators
+  int nlev(int k) const { return h_.host[k].n; }
+  void applyA(int k, const double* X, int ldx, double* Y, int ldy, int b);
+  void applyM(int k, const double* X, int ldx, double* Y, int ldy, int b);
+  void applyB(int k, const double* X, int ldx, double* Y, int ldy, int b);
+
+  // solvers (columns independent, scalars on the device)
+  enum class OpKind { A, M, B };
+  void cg(int k, OpKind op, const double* B, int ldb, double* X, int ldx, int n, int b,
+          double tol, bool use_x0, const int* parent_active, int fixed_iters,
+          const std::string& tag, std::vector<int>* iters);
+  void pcg(int k, const double* B, int ldb, double* X, int ldx, int b, double tol, bool use_x0,
+           std::vector<int>* iters);
+
+  // Lanczos / extension / refinement
+  struct Lanczos;
+  void lanczos_init(Lanczos& L, int k, const double* Vini, int mi, int cap_cols);
+  void lanczos_random(Lanczos& L, double* out);
+  void lanczos_orth(Lanczos& L, double* w, int jcols, std::vector<double>* hlast);
+  double mnorm2(int k, const double* x);
+  void lanczos_steps(Lanczos& L, int nsteps);
+  bool ritz_converged(Lanczos& L, int nwant, double eps, bool relative);
+  void restart(Lanczos& L, int kkeep, int p);
+  void extend(int k, double*& V, std::vector<double>& D, int& m, int m_tar, double eps,
+              double mu_ex, int d, bool relative);
+  void multiplicity_check(double*& V, std::vector<double>& D, int m, double eps, int d);
+  void refine(int k, double*& V, std::vector<double>& D, int& m, double eps, double mu_h,
+              double lam_max_M, double gamma);
+  void mqr(int k, double* F, int n, int b, const std::string& tag);
+  void final_pairs(double* V, const std::vector<double>& D, int m, int nev, double tol,
+                   double* evals, double* evecs);
+
+  void sync() { MMD_HIP(hipStreamSynchronize(s_)); }
+  template <typename T>
+  void d2h(T* dst, const T* src, size_t n) {
+    MMD_HIP(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToHost, s_));
+  }
+  template <typename T>
+  void h2d(T* dst, const T* src, size_t n) {
+    MMD_HIP(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, s_));
+  }
+
+  mmd_handle& h_;
+  hipStream_t s_;
+  eig_opts o_;
+  eig_stats* st_;
+  Pool pool_;
+  HBuf<double> hd_;
+  HBuf<int> hi_;
+  int inner_iters_ = 16;
+  int cur_level_ = 0;
+  int64_t draws_[MMD_MAX_LEVELS] = {};
+};
+
+}  // namespace mmd

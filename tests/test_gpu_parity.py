@@ -1,0 +1,196 @@
+"""GPU path (through the C ABI) against the CPU oracle, element by element.
+
+Inputs are seeded and synthetic (workloads package); expected values come only
+from the oracle package or from closed forms.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+import workloads as wl
+from oracle import dense, krylov, mmd as mm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _t(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+# ------------------------------------------------------------------- SpMM kernel
+@pytest.mark.parametrize("shape", [(1, 1, 1), (37, 50, (0, 6)), (1000, 1000, (3, 14)),
+                                   (3001, 2000, (40, 120)), (513, 700, (0, 250))])
+@pytest.mark.parametrize("b", [1, 3, 7, 32, 64, 130])
+def test_spmm_random(torch_cuda, shape, b):
+    torch = torch_cuda
+    from paper_1804_03415_amd import spmm
+    nr, nc, per = shape
+    rp, ci, v = wl.random_csr(nr, nc, per, seed=nr + b, empty_frac=0.1)
+    X = wl.random_block(nc, b, seed=b)
+    A = sp.csr_matrix((v, ci, rp), shape=(nr, nc))
+    ref = A @ X
+    Y = spmm(_t(torch, rp), _t(torch, ci), _t(torch, v), _t(torch, X), n_cols=nc).cpu().numpy()
+    bound = 1e-14 * (abs(A) @ np.abs(X)) + 1e-300
+    assert np.all(np.abs(Y - ref) <= 8 * bound)
+
+
+# ------------------------------------------------------------------- decomposition parity
+CASES = {
+    "grid2d_32": (lambda: wl.grid2d(32), dict(levels=3, exact_max_n=4096)),
+    "rgg_2000": (lambda: wl.rgg(2000, 0), dict(levels=3)),
+    "knn_1500": (lambda: wl.knn_gmm(1500, 10, 1), dict(levels=2)),
+    "grid3d_8": (lambda: wl.grid3d_lognormal(8, 0), dict(levels=2, grid_blocks=(2, 2))),
+}
+
+
+def _oracle_build(p, kw):
+    return mm.build_mmd(p.scipy(), coords=None if p.grid else p.coords, grid=p.grid, **kw)
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def built(request, torch_cuda):
+    from paper_1804_03415_amd import Decomposition
+    make, kw = CASES[request.param]
+    p = make()
+    dec = Decomposition.from_problem(p, **kw)
+    return p, kw, dec, _oracle_build(p, kw)
+
+
+def test_build_parity(built):
+    p, kw, dec, M = built
+    info = dec.info()
+    assert info["sizes"] == [l.n for l in M.levels]
+    assert np.allclose(info["eps"], M.eps, rtol=1e-10)
+    for k in range(1, M.K + 1):
+        for which, ref in ((0, M.levels[k].A), (1, M.levels[k].M), (2, M.levels[k].Psi)):
+            rp, ci, v, shape = dec.export(k, which)
+            X = sp.csr_matrix((v, ci, rp), shape=shape)
+            assert X.shape == ref.shape
+            assert X.nnz == ref.nnz
+            assert abs(X - ref).max() <= 1e-11 * abs(ref).max()
+
+
+def test_level_operators(built, torch_cuda):
+    torch = torch_cuda
+    p, kw, dec, M = built
+    b = 5
+    for k in range(0, M.K + 1):
+        lev = M.levels[k]
+        X = wl.random_block(lev.n, b, seed=k)
+        refA = krylov.EdgeForm(p.scipy()) @ X if k == 0 else lev.A @ X
+        Y = dec.apply(k, "A", _t(torch, X)).cpu().numpy()
+        assert np.abs(Y - refA).max() <= 1e-12 * np.abs(refA).max()
+        if k >= 1:
+            Y = dec.apply(k, "M", _t(torch, X)).cpu().numpy()
+            assert np.abs(Y - lev.M @ X).max() <= 1e-12 * np.abs(lev.M @ X).max()
+        if k < M.K:
+            up = M.levels[k + 1]
+            Y = dec.apply(k, "Ut", _t(torch, X)).cpu().numpy()
+            ref = up.Ut_apply(X)
+            assert np.abs(Y - ref).max() <= 1e-13 * np.abs(ref).max()
+            Xr = wl.random_block(up.nb(), b, seed=10 + k)
+            Y = dec.apply(k, "U", _t(torch, Xr)).cpu().numpy()
+            ref = up.U_apply(Xr)
+            assert np.abs(Y - ref).max() <= 1e-13 * np.abs(ref).max()
+            Aop = krylov.EdgeForm(p.scipy()) if k == 0 else lev.A
+            ref = up.Ut_apply(Aop @ up.U_apply(Xr))
+            Y = dec.apply(k, "B", _t(torch, Xr)).cpu().numpy()
+            assert np.abs(Y - ref).max() <= 1e-12 * np.abs(ref).max()
+            Xc = wl.random_block(up.n, b, seed=20 + k)
+            Y = dec.apply(k, "Psi", _t(torch, Xc)).cpu().numpy()
+            ref = up.Psi @ Xc
+            assert np.abs(Y - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_level_solves(built, torch_cuda):
+    torch = torch_cuda
+    p, kw, dec, M = built
+    b = 4
+    tol = 1e-10
+    for k in range(0, M.K + 1):
+        lev = M.levels[k]
+        Ad = p.scipy().toarray() if k == 0 else lev.A.toarray()
+        rhs = wl.random_block(lev.n, b, seed=30 + k)
+        X, it = dec.solve(k, 0, _t(torch, rhs), tol=tol)
+        X = X.cpu().numpy()
+        # true residual within the solver's stop rule plus the attainable FP64
+        # accuracy of a recursive-residual Krylov method, c u ||A|| ||x|| / ||b||
+        nb = np.linalg.norm(rhs, axis=0)
+        floor = 50 * 2.2e-16 * np.linalg.norm(Ad, 2) * np.linalg.norm(X, axis=0) / nb
+        res = np.linalg.norm(rhs - Ad @ X, axis=0) / nb
+        assert np.all(res <= 1.5 * tol + floor)
+        Aop = krylov.EdgeForm(p.scipy()) if k == 0 else lev.A
+        for c in range(b):
+            xo = krylov.pcg(lambda v: Aop @ v, rhs[:, c], lev.M, None, tol)
+            # same system, same stop rule: the two solutions agree to the solve accuracy
+            err = np.linalg.norm(X[:, c] - xo) / np.linalg.norm(xo)
+            cond = np.linalg.cond(Ad) if lev.n <= 4096 else 1e8
+            assert err <= 3 * tol * cond
+        if k < M.K:
+            up = M.levels[k + 1]
+            U = up.U_apply(np.eye(up.nb()))
+            B = U.T @ Ad @ U
+            r2 = wl.random_block(up.nb(), b, seed=40 + k)
+            G, it = dec.solve(k, 1, _t(torch, r2), tol=tol)
+            G = G.cpu().numpy()
+            nb2 = np.linalg.norm(r2, axis=0)
+            floor = 50 * 2.2e-16 * np.linalg.norm(B, 2) * np.linalg.norm(G, axis=0) / nb2
+            res = np.linalg.norm(r2 - B @ G, axis=0) / nb2
+            assert np.all(res <= 1.5 * tol + floor)
+
+
+# ------------------------------------------------------------------- eigensolver
+def _run_both(p, nev, tol, kw):
+    from paper_1804_03415_amd import Decomposition
+    dec = Decomposition.from_problem(p, **kw)
+    lam, V, st = dec.eig_leftmost(nev, tol=tol)
+    okw = dict(kw)
+    okw["coords"] = None if p.grid else p.coords
+    okw["grid"] = p.grid
+    lo, Vo = krylov.eig_leftmost(p.scipy(), nev, tol, mmd_kwargs=okw)
+    return lam, V.cpu().numpy().T, st, lo, Vo
+
+
+def _closed_2d(n, count):
+    j = np.arange(1, n + 1)
+    s = 4 * np.sin(j * np.pi / (2 * (n + 1))) ** 2
+    return np.sort((s[:, None] + s[None, :]).ravel())[:count]
+
+
+def test_eig_c1_grid(torch_cuda):
+    p = wl.grid2d(32)
+    lam, V, st, lo, Vo = _run_both(p, 50, 1e-10, dict(levels=3, exact_max_n=4096))
+    ref = _closed_2d(32, 50)
+    assert np.max(np.abs(lam - ref) / ref) < 1e-10
+    assert np.max(np.abs(lam - lo) / lo) < 1e-10
+    ang, cl = dense.cluster_angles(lo, Vo, V)
+    assert ang.max() < 1e-8
+    assert dense.rel_residuals(p.scipy(), lam, V).max() < 1e-8
+    assert np.allclose(np.linalg.norm(V, axis=0), 1.0, atol=1e-13)
+
+
+@pytest.mark.parametrize("case", ["rgg", "knn", "grid3d_const"])
+def test_eig_small(torch_cuda, case):
+    if case == "rgg":
+        p, nev, kw = wl.rgg(400, 11, mean_degree=5), 30, dict(levels=2)
+    elif case == "knn":
+        p, nev, kw = wl.knn_gmm(300, 10, 1), 15, dict(levels=2)
+    else:
+        p, nev, kw = wl.grid3d_lognormal(8, 0, sigma=0.0), 20, dict(levels=1, grid_blocks=(2,))
+    lam, V, st, lo, Vo = _run_both(p, nev, 1e-11, kw)
+    A = p.scipy()
+    null = np.abs(lo - 1e-6) < 1e-12
+    assert np.sum(np.abs(lam - 1e-6) < 1e-12) == np.sum(null)
+    assert np.max(np.abs(lam[~null] - lo[~null]) / lo[~null]) < 1e-10
+    ang, cl = dense.cluster_angles(lo, Vo, V)
+    full = [i for i, c in enumerate(cl) if c[-1] < nev - 1]
+    assert ang[full].max() < 1e-8
+    assert dense.rel_residuals(A, lam, V).max() < 1e-8
