@@ -1,0 +1,183 @@
+"""Benchmark: leftmost eigenpairs/s of the hierarchical eigensolver on one MI355X.
+
+Workload (default): random geometric graph Laplacian + 1e-6 I, n = 100,000
+points in the unit square, mean degree ~10, weights exp(-d^2/r^2), the 300
+smallest eigenpairs, accepted when every pair has
+||A v - lambda v|| / (lambda ||v||) <= 1e-8.  A step is one full eigensolve
+(all levels: coarsest solve, reform, refinement, extension, output step) on
+the decomposition built once beforehand.  Inputs are resident in HBM before
+the timed region starts.
+
+Extra objects on the JSON line:
+  roofline      the dominant kernel (the level-0 SpMM of the refinement block
+                PCG) timed with HIP events on the stream it runs on, against
+                the 8 TB/s HBM peak; traffic = HBM bytes from rocprofv3
+                counters (null unless supplied with --traffic-bytes).
+  cpu_baseline  the CPU oracle timed on this host on a bounded sample of the
+                same workload (see --cpu-sample-nev).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=100000)
+    ap.add_argument("--nev", type=int, default=300)
+    ap.add_argument("--tol", type=float, default=1e-9)
+    ap.add_argument("--levels", type=int, default=3)
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--cpu-sample-nev", type=int, default=8)
+    ap.add_argument("--traffic-bytes", type=float, default=None,
+                    help="HBM bytes per launch of the dominant kernel from rocprofv3 counters")
+    ap.add_argument("--verbose", type=int, default=0)
+    return ap.parse_args()
+
+
+def spmm_bytes_edge(n, nnz_off, b):
+    """Algorithmic HBM bytes of one edge-form SpMM launch, FP64 values, int32 indices:
+    weights + columns (12 B per off-diagonal), row pointers (4 B per row), s (8 B per row),
+    X read once and Y written once (8 B per entry each)."""
+    return 12.0 * nnz_off + 4.0 * (n + 1) + 8.0 * n + 16.0 * n * b
+
+
+def dominant_kernel_roofline(dec, p, b, reps=50):
+    """Average duration of the level-0 edge-form SpMM on a block of b columns."""
+    import torch
+    X = torch.randn(p.n, b, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        dec.apply(0, "A", X)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    Y = None
+    e0.record(s)
+    for _ in range(reps):
+        Y = dec.apply(0, "A", X)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del Y
+    nnz_off = p.nnz - p.n
+    byts = spmm_bytes_edge(p.n, nnz_off, b)
+    return ms, byts
+
+
+def cpu_baseline(p, nev, tol, levels):
+    """The oracle, as it stands, on the same matrix for the first `nev` pairs."""
+    import oracle.krylov as ok
+    t = time.perf_counter()
+    lam, V = ok.eig_leftmost(p.scipy(), nev, tol, mmd_kwargs=dict(
+        coords=p.coords, levels=levels, targets=(4, 8)))
+    dt = time.perf_counter() - t
+    return nev / dt, dt
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads
+    from paper_1804_03415_amd import Decomposition
+
+    torch.cuda.set_device(0)
+    p = workloads.rgg(a.n, 0)
+    t = time.perf_counter()
+    dec = Decomposition.from_problem(p, levels=a.levels, targets=(4, 8))
+    t_build = time.perf_counter() - t
+    info = dec.info()
+    if a.verbose:
+        print("decomposition", info, "build %.2fs" % t_build, file=sys.stderr, flush=True)
+    for w in range(a.warmup):
+        lam, V, st = dec.eig_leftmost(a.nev, tol=a.tol)
+        if a.verbose:
+            print("warmup %d: %.3fs" % (w, st["seconds_total"]), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for s in range(a.steps):
+        lam, V, st = dec.eig_leftmost(a.nev, tol=a.tol)
+        stats.append(st)
+        if a.verbose:
+            print("step %d: %.3fs" % (s, st["seconds_total"]), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = 1000.0 * elapsed / a.steps
+    value = a.nev * a.steps / elapsed
+
+    # acceptance: every returned pair meets the residual target (FP64, CSR form)
+    A = p.scipy()
+    Vh = V.cpu().numpy().T
+    rho = np.linalg.norm(A @ Vh - Vh * lam[None, :], axis=0) / (np.abs(lam) * np.linalg.norm(Vh, axis=0))
+    ncomp_null = int(np.sum(np.abs(lam - 1e-6) < 1e-12))
+
+    # dominant kernel: level-0 SpMM on the refinement block
+    b_dom = a.nev
+    ms_k, byts = dominant_kernel_roofline(dec, p, b_dom)
+    achieved = byts / (ms_k * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": "k_spmm edge form, level 0, b=%d" % b_dom,
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": a.traffic_bytes, "bytes_per_launch": byts,
+            "avg_launch_us": round(ms_k * 1000.0, 2)}
+
+    cpu = None
+    if a.cpu_baseline:
+        v_cpu, dt_cpu = cpu_baseline(p, a.cpu_sample_nev, a.tol, a.levels)
+        cpu = {"value": round(v_cpu, 4), "unit": "eigenpairs/s", "cores": os.cpu_count(),
+               "kind": "oracle",
+               "sample": "oracle (numpy/scipy FP64) on the same n=%d RGG matrix, first %d "
+                         "eigenpairs, tol %.0e, %.1fs" % (a.n, a.cpu_sample_nev, a.tol, dt_cpu)}
+        try:
+            import threadpoolctl
+            info_t = threadpoolctl.threadpool_info()
+            cpu["cores"] = max([x.get("num_threads", 1) for x in info_t] + [1])
+        except Exception:
+            pass
+
+    out = {
+        "metric": "eigenpairs/s at rel. residual 1e-8 (FP64)",
+        "value": round(value, 3),
+        "unit": "eigenpairs/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_step, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "rgg_laplacian_n%d_nev%d" % (a.n, a.nev), "n": a.n,
+                   "nnz": int(p.nnz), "nev": a.nev, "tol": a.tol,
+                   "levels": info["sizes"], "build_s": round(t_build, 2)},
+        "max_rel_residual": float(rho.max()),
+        "residual_ok": bool(rho.max() <= 1e-8),
+        "null_cluster": ncomp_null,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    if a.verbose:
+        print(json.dumps(stats[-1]), file=sys.stderr)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
