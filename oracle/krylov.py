@@ -428,8 +428,17 @@ def keep_count(D, mu_h, gamma):
     return mh
 
 
-def refine(ops: LevelOps, Vl, Dl, eps, mu_h, lam_max_M, gamma=2.0 / 3.0, max_iter=200):
-    """Eigenpair Refinement (Alg. 5): level-(k+1) pairs reformed to level k -> level-k pairs."""
+def refine(ops: LevelOps, Vl, Dl, eps, mu_h, lam_max_M, gamma=2.0 / 3.0, max_iter=200,
+           eps_solve=None):
+    """Eigenpair Refinement (Alg. 5): level-(k+1) pairs reformed to level k -> level-k pairs.
+
+    eps_solve (default eps) is the PCG tolerance; on level 0 the driver passes
+    0.1 eps so the stop test at eps lies above the noise of the solves.  The
+    loop also stops when the distance has stagnated below 10 eps (no 10%
+    decrease over 5 iterations): the attainable floor of inexact solves.
+    """
+    if eps_solve is None:
+        eps_solve = eps
     st = ops.st
     ml = Vl.shape[1]
     st["ref_in"] += ml
@@ -441,19 +450,20 @@ def refine(ops: LevelOps, Vl, Dl, eps, mu_h, lam_max_M, gamma=2.0 / 3.0, max_ite
     G = np.zeros((up.nb(), ml))
     for i in range(ml):
         rhs = up.Ut_apply(MQ[:, i])
-        G[:, i], it = cg(ops.applyB, rhs, None, eps)
+        G[:, i], it = cg(ops.applyB, rhs, None, eps_solve)
         st["cg_B_calls"] += 1
         st["cg_B_iters"] += it
     F = Vl * Dl[None, :] + up.U_apply(G)
     mu_prev = Dl.copy()
     Qprev = None
     thresh = eps / np.sqrt(lam_max_M)
+    hist = []
     for it in range(1, max_iter + 1):
         Q = mqr(F, ops.M)
         W = ops.applyM(Q)
         F = np.zeros_like(Q)
         for i in range(ml):
-            F[:, i] = pcg(ops.applyA, W[:, i], ops.M, mu_prev[i] * Q[:, i], eps, st)
+            F[:, i] = pcg(ops.applyA, W[:, i], ops.M, mu_prev[i] * Q[:, i], eps_solve, st)
         S = W.T @ F
         D, P = eig_desc(S)
         mh = keep_count(D, mu_h, gamma)
@@ -464,7 +474,10 @@ def refine(ops: LevelOps, Vl, Dl, eps, mu_h, lam_max_M, gamma=2.0 / 3.0, max_ite
         if Qprev is not None:
             X = Qprev[:, :mh].T @ ops.applyM(Q[:, :mh])
             E = Q[:, :mh] - Qprev[:, :mh] @ X
-            done = np.linalg.norm(E) < thresh
+            dist = np.linalg.norm(E)
+            hist.append(dist)
+            done = dist < thresh or (len(hist) > 5 and dist < 10 * thresh
+                                     and dist > 0.9 * hist[-6])
         Qprev = Q
         mu_prev = D
         if done:
@@ -546,7 +559,8 @@ def eig_leftmost(A, nev, tol, mmd: Optional[MMD] = None, alpha=3.0, beta=1.0, c=
         ops = LevelOps(mmd, k, sch.eps_op[k], stats, E0)
         V = mmd.levels[k + 1].Psi @ V
         V, D = refine(ops, V, D, sch.eps_op[k], sch.mu_re[k], mmd.levels[k].lam_max_M,
-                      gamma=(1.0 + beta) / alpha)
+                      gamma=(1.0 + beta) / alpha,
+                      eps_solve=0.1 * sch.eps_op[k] if k == 0 else sch.eps_op[k])
         V, D = extend(ops, V, D, nev, sch.eps_op[k], sch.mu_ex[k], sch.d[k], c,
                       relative=(k == 0), seed=seed)
     if K == 0:

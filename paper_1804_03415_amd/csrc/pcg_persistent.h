@@ -1,0 +1,30 @@
+// Persistent cooperative CG / flexible PCG for one right-hand side.
+#pragma once
+
+#include "kernels.h"
+
+namespace mmd {
+
+struct Pcg1Args {
+  CsrView A;          // level operator (edge form on level 0)
+  CsrView M;          // preconditioner M^(k); rowptr == nullptr: plain CG
+  int n = 0;
+  const double* b = nullptr;
+  double* x = nullptr;  // x0 on entry when use_x0, solution on exit
+  double *r = nullptr, *z = nullptr, *zo = nullptr, *p = nullptr, *q = nullptr;
+  double *ri = nullptr, *pi = nullptr, *qi = nullptr;  // inner CG work
+  double* red = nullptr;  // pcg1_red_size() doubles
+  double tol = 0.0, tol_in = 0.0;
+  int maxit = 100000, maxit_in = 500, use_x0 = 0;
+  int lpr_a = 8, lpr_m = 8;
+  int* out = nullptr;     // [3]: outer iterations, inner iterations, flag (1 not SPD, 2 cap)
+  double* res = nullptr;  // [2]: final ||r||^2, ||b||^2
+};
+
+// Launch on stream s (asynchronous).  Stop rule ||r|| <= tol ||b||; the inner
+// CG stops at ||r_in|| <= tol_in ||r||.
+void pcg1(Pcg1Args a, hipStream_t s);
+size_t pcg1_red_size();
+int pcg1_grid();
+
+}  // namespace mmd

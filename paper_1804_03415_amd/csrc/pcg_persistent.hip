@@ -1,0 +1,324 @@
+// Single-right-hand-side CG / flexible PCG as one persistent cooperative kernel.
+//
+// The Lanczos operator OP (Section 4) applies pcg(A, M v, M, 0, eps) to one
+// vector per step; launched as separate kernels every CG iteration costs
+// several kernel boundaries, so the whole solve (outer PCG and the inner CG
+// on M) runs here in one cooperative launch with grid-wide barriers.
+//
+// Barrier discipline: every block executes exactly the same sequence of
+// grid.sync() calls.  Each loop decision (convergence, curvature check,
+// iteration caps) is taken from scalars that every block computes from the
+// same global partial sums in the same order, so all blocks agree.
+#include <hip/hip_cooperative_groups.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "common.h"
+#include "pcg_persistent.h"
+
+namespace mmd {
+
+namespace {
+
+namespace cg = cooperative_groups;
+
+constexpr int kThreads = 256;
+constexpr int kWave = 64;
+
+struct Ctx {
+  cg::grid_group grid;
+  int nblk, blk, gtid, gsize, gwave, nwave, lane;
+  double* red;   // two disjoint slots of 2*nblk partial sums
+  int slot;
+};
+
+// Sum of v over the block, result valid in every thread.
+__device__ inline double block_sum(double v, double* sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  const int w = threadIdx.x / kWave;
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int q = 0; q < kThreads / kWave; ++q) t += sh[q];
+  __syncthreads();
+  return t;
+}
+
+// Grid-wide sum: each block contributes its partial, barrier, then every block
+// adds the partials in the same fixed order.
+__device__ inline double grid_sum(Ctx& c, double part, double* sh) {
+  const double b = block_sum(part, sh);
+  double* r = c.red + (size_t)c.slot * 2 * c.nblk;  // slot regions are disjoint
+  if (threadIdx.x == 0) r[c.blk] = b;
+  c.grid.sync();
+  double t = 0.0;
+  for (int j = threadIdx.x; j < c.nblk; j += kThreads) t += r[j];
+  const double s = block_sum(t, sh);
+  c.slot ^= 1;
+  return s;
+}
+
+// Two grid sums sharing one barrier.
+__device__ inline void grid_sum2(Ctx& c, double p1, double p2, double* sh, double& s1,
+                                 double& s2) {
+  const double b1 = block_sum(p1, sh);
+  const double b2 = block_sum(p2, sh);
+  double* r = c.red + (size_t)c.slot * c.nblk * 2;
+  if (threadIdx.x == 0) {
+    r[c.blk] = b1;
+    r[c.nblk + c.blk] = b2;
+  }
+  c.grid.sync();
+  double t1 = 0.0, t2 = 0.0;
+  for (int j = threadIdx.x; j < c.nblk; j += kThreads) {
+    t1 += r[j];
+    t2 += r[c.nblk + j];
+  }
+  s1 = block_sum(t1, sh);
+  s2 = block_sum(t2, sh);
+  c.slot ^= 1;
+}
+
+// Row value (A x)_row for LPR lanes per row; lane sub-index s.  Edge form when
+// diag != null: s_i x_i + sum_j w_ij (x_i - x_j).
+__device__ inline double row_apply(const CsrView& A, const double* __restrict__ x, int row,
+                                   int s, int lpr) {
+  double acc = 0.0;
+  const int lo = A.rowptr[row], hi = A.rowptr[row + 1];
+  if (A.diag) {
+    const double xi = x[row];
+    for (int k = lo + s; k < hi; k += lpr) acc += A.val[k] * (xi - x[A.col[k]]);
+  } else {
+    for (int k = lo + s; k < hi; k += lpr) acc += A.val[k] * x[A.col[k]];
+  }
+  for (int off = 1; off < lpr; off <<= 1) acc += __shfl_xor(acc, off, kWave);
+  if (A.diag) acc += A.diag[row] * x[row];
+  return acc;
+}
+
+// Fused CG direction step: w = A rr (all rows of rr complete), then per row
+// p = rr + beta p, q = w + beta q; returns this thread's share of p.q.
+__device__ inline double dir_step(Ctx& c, const CsrView& A, int lpr, const double* rr, double* p,
+                                  double* q, double beta, bool first) {
+  const int R = kWave / lpr;
+  const int s = c.lane % lpr;
+  const int r = c.lane / lpr;
+  const int groups = (A.n_rows + R - 1) / R;
+  double part = 0.0;
+  for (int g = c.gwave; g < groups; g += c.nwave) {
+    const int row = g * R + r;
+    // all lanes of a row-group are inside the loop together (uniform trip count)
+    double w = 0.0;
+    if (row < A.n_rows) w = row_apply(A, rr, row, s, lpr);
+    if (row < A.n_rows && s == 0) {
+      const double pn = first ? rr[row] : rr[row] + beta * p[row];
+      const double qn = first ? w : w + beta * q[row];
+      p[row] = pn;
+      q[row] = qn;
+      part += pn * qn;
+    }
+  }
+  return part;
+}
+
+__global__ __launch_bounds__(kThreads) void k_pcg1(Pcg1Args a) {
+  __shared__ double sh[kThreads / kWave];
+  Ctx c{cg::this_grid(), (int)gridDim.x, (int)blockIdx.x,
+        (int)(blockIdx.x * blockDim.x + threadIdx.x), (int)(gridDim.x * blockDim.x),
+        (int)((blockIdx.x * blockDim.x + threadIdx.x) / kWave),
+        (int)((gridDim.x * blockDim.x) / kWave), (int)(threadIdx.x & (kWave - 1)), a.red, 0};
+  const int n = a.n;
+  const bool pre = a.M.rowptr != nullptr;
+  // r = b - A x0 (or b with x = 0); ||b||^2, ||r||^2
+  double pb = 0.0, pr = 0.0;
+  if (a.use_x0) {
+    // w stored in q temporarily
+    const int R = kWave / a.lpr_a;
+    const int s = c.lane % a.lpr_a, rr = c.lane / a.lpr_a;
+    const int groups = (n + R - 1) / R;
+    for (int g = c.gwave; g < groups; g += c.nwave) {
+      const int row = g * R + rr;
+      double w = 0.0;
+      if (row < n) w = row_apply(a.A, a.x, row, s, a.lpr_a);
+      if (row < n && s == 0) a.q[row] = w;
+    }
+    c.grid.sync();
+    for (int i = c.gtid; i < n; i += c.gsize) {
+      const double ri = a.b[i] - a.q[i];
+      a.r[i] = ri;
+      pb += a.b[i] * a.b[i];
+      pr += ri * ri;
+    }
+  } else {
+    for (int i = c.gtid; i < n; i += c.gsize) {
+      a.x[i] = 0.0;
+      a.r[i] = a.b[i];
+      pb += a.b[i] * a.b[i];
+    }
+    pr = pb;
+  }
+  double bn2, rr2;
+  grid_sum2(c, pb, pr, sh, bn2, rr2);
+  const double tol2 = a.tol * a.tol * bn2;
+  int it = 0, inner_total = 0, flag = 0;
+  bool done = !(bn2 > 0.0) || rr2 <= tol2;
+  if (!pre) {
+    // ---------------- plain CG
+    double rr = rr2, beta = 0.0;
+    bool first = true;
+    while (!done) {
+      const double ppq = dir_step(c, a.A, a.lpr_a, a.r, a.p, a.q, beta, first);
+      first = false;
+      const double pq = grid_sum(c, ppq, sh);
+      if (!(pq > 0.0)) {
+        flag = 1;
+        break;
+      }
+      const double al = rr / pq;
+      double prr = 0.0;
+      for (int i = c.gtid; i < n; i += c.gsize) {
+        a.x[i] += al * a.p[i];
+        const double ri = a.r[i] - al * a.q[i];
+        a.r[i] = ri;
+        prr += ri * ri;
+      }
+      const double rn = grid_sum(c, prr, sh);
+      ++it;
+      beta = rn / rr;
+      rr = rn;
+      rr2 = rn;
+      if (rn <= tol2) break;
+      if (it >= a.maxit) {
+        flag = 2;
+        break;
+      }
+    }
+  } else {
+    // ---------------- flexible PCG with an inner CG on M (zero start)
+    const double tol_in2 = a.tol_in * a.tol_in;
+    auto inner = [&](double rnorm2) {
+      // z = M^-1 r approximately; ri = r, pi/qi directions, z accumulates
+      for (int i = c.gtid; i < n; i += c.gsize) {
+        a.z[i] = 0.0;
+        a.ri[i] = a.r[i];
+      }
+      c.grid.sync();
+      double rri = rnorm2, bi = 0.0;
+      bool f = true;
+      int k = 0;
+      while (rri > tol_in2 * rnorm2 && k < a.maxit_in) {
+        const double ppq = dir_step(c, a.M, a.lpr_m, a.ri, a.pi, a.qi, bi, f);
+        f = false;
+        const double pq = grid_sum(c, ppq, sh);
+        if (!(pq > 0.0)) break;
+        const double al = rri / pq;
+        double prr = 0.0;
+        for (int i = c.gtid; i < n; i += c.gsize) {
+          a.z[i] += al * a.pi[i];
+          const double ri = a.ri[i] - al * a.qi[i];
+          a.ri[i] = ri;
+          prr += ri * ri;
+        }
+        const double rn = grid_sum(c, prr, sh);
+        bi = rn / rri;
+        rri = rn;
+        ++k;
+      }
+      inner_total += k;
+    };
+    if (!done) {
+      inner(rr2);
+      double prz = 0.0;
+      for (int i = c.gtid; i < n; i += c.gsize) prz += a.r[i] * a.z[i];
+      double rz = grid_sum(c, prz, sh);
+      double beta = 0.0;
+      bool first = true;
+      while (true) {
+        const double ppq = dir_step(c, a.A, a.lpr_a, a.z, a.p, a.q, beta, first);
+        first = false;
+        const double pq = grid_sum(c, ppq, sh);
+        if (!(pq > 0.0)) {
+          flag = 1;
+          break;
+        }
+        const double al = rz / pq;
+        double prr = 0.0;
+        for (int i = c.gtid; i < n; i += c.gsize) {
+          a.x[i] += al * a.p[i];
+          const double ri = a.r[i] - al * a.q[i];
+          a.r[i] = ri;
+          a.zo[i] = a.z[i];
+          prr += ri * ri;
+        }
+        const double rn = grid_sum(c, prr, sh);
+        ++it;
+        rr2 = rn;
+        if (rn <= tol2) break;
+        if (it >= a.maxit) {
+          flag = 2;
+          break;
+        }
+        inner(rn);
+        double p1 = 0.0, p2 = 0.0;
+        for (int i = c.gtid; i < n; i += c.gsize) {
+          p1 += a.r[i] * a.z[i];
+          p2 += a.r[i] * a.zo[i];
+        }
+        double rzn, rzo;
+        grid_sum2(c, p1, p2, sh, rzn, rzo);
+        beta = (rzn - rzo) / rz;
+        rz = rzn;
+      }
+    }
+  }
+  if (c.gtid == 0) {
+    a.out[0] = it;
+    a.out[1] = inner_total;
+    a.out[2] = flag;
+    a.res[0] = rr2;
+    a.res[1] = bn2;
+  }
+}
+
+int lanes_for(double avg) {
+  if (avg <= 10.0) return 8;
+  if (avg <= 24.0) return 16;
+  if (avg <= 48.0) return 32;
+  return 64;
+}
+
+}  // namespace
+
+int pcg1_grid() {
+  static int cached = 0;
+  if (cached) return cached;
+  int dev = 0;
+  MMD_HIP(hipGetDevice(&dev));
+  int coop = 0;
+  MMD_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+  MMD_REQUIRE(coop != 0, MMD_EHIP, "device does not support cooperative launches");
+  int cus = 0;
+  MMD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  int per = 0;
+  MMD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_pcg1, kThreads, 0));
+  MMD_REQUIRE(per > 0, MMD_EHIP, "persistent PCG kernel cannot be resident");
+  cached = cus * std::min(per, 2);
+  return cached;
+}
+
+void pcg1(Pcg1Args a, hipStream_t s) {
+  const int grid = std::min(pcg1_grid(), std::max(1, (a.n + kThreads - 1) / kThreads));
+  a.lpr_a = lanes_for(a.A.avg_row);
+  a.lpr_m = a.M.rowptr ? lanes_for(a.M.avg_row) : 8;
+  void* args[] = {&a};
+  MMD_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_pcg1), dim3(grid),
+                                     dim3(kThreads), args, 0, s));
+}
+
+size_t pcg1_red_size() { return 4 * (size_t)4096; }
+
+}  // namespace mmd

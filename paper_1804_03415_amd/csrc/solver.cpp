@@ -10,11 +10,14 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <numeric>
 
 #include "dense.h"
+#include "pcg_persistent.h"
 
 namespace mmd {
 
@@ -75,6 +78,15 @@ void tri_of(const std::vector<double>& T, int ld, int m, std::vector<double>& d,
   e.resize(m > 0 ? m - 1 : 0);
   for (int i = 0; i < m; ++i) d[i] = T[(size_t)i * ld + i];
   for (int i = 0; i + 1 < m; ++i) e[i] = T[(size_t)(i + 1) * ld + i];
+}
+
+// MMDEIG_LOG=1 prints per-level progress of the driver to stderr.
+bool log_on() {
+  static const bool on = [] {
+    const char* e = std::getenv("MMDEIG_LOG");
+    return e && e[0] && e[0] != '0';
+  }();
+  return on;
 }
 
 int keep_count(const std::vector<double>& D, int ml, double mu_h, double gamma) {
@@ -211,9 +223,47 @@ void Solver::cg(int k, OpKind op, const double* B, int ldb, double* X, int ldx, 
   }
 }
 
+bool Solver::pcg_single(int k, const double* B, double* X, double tol, bool use_x0,
+                        std::vector<int>* iters) {
+  const int n = nlev(k);
+  Pcg1Args a;
+  a.A = h_.dev[k].A;
+  if (k > 0) a.M = h_.dev[k].M;
+  a.n = n;
+  a.b = B;
+  a.x = X;
+  a.r = pool_.d("p1:r", n);
+  a.z = pool_.d("p1:z", n);
+  a.zo = pool_.d("p1:zo", n);
+  a.p = pool_.d("p1:p", n);
+  a.q = pool_.d("p1:q", n);
+  a.ri = pool_.d("p1:ri", n);
+  a.pi = pool_.d("p1:pi", n);
+  a.qi = pool_.d("p1:qi", n);
+  a.red = pool_.d("p1:red", pcg1_red_size());
+  a.tol = tol;
+  a.tol_in = 0.1 * tol;
+  a.use_x0 = use_x0 ? 1 : 0;
+  a.out = pool_.i("p1:out", 3);
+  a.res = pool_.d("p1:res", 2);
+  pcg1(a, s_);
+  hi_.ensure(4);
+  d2h(hi_.p, a.out, 3);
+  sync();
+  MMD_REQUIRE(hi_.p[2] != 1, MMD_ENOTSPD, "PCG curvature p^T A p <= 0");
+  MMD_REQUIRE(hi_.p[2] != 2, MMD_ENOCONV, "PCG reached the iteration cap");
+  if (st_ && k > 0) st_->cg_M_iters[k] += hi_.p[1];
+  if (iters) iters->assign(1, hi_.p[0]);
+  return true;
+}
+
 void Solver::pcg(int k, const double* B, int ldb, double* X, int ldx, int b, double tol,
                  bool use_x0, std::vector<int>* iters) {
   const int n = nlev(k);
+  if (b == 1 && ldb == 1 && ldx == 1 && use_persistent_) {
+    pcg_single(k, B, X, tol, use_x0, iters);
+    return;
+  }
   if (k == 0) {
     cg(0, OpKind::A, B, ldb, X, ldx, n, b, tol, use_x0, nullptr, 0, "cg0", iters);
     return;
@@ -500,6 +550,9 @@ void Solver::extend(int k, double*& V, std::vector<double>& D, int& m, int m_tar
   }
   const int mnew = kcur;
   converge(mnew, std::min(c * mnew, cap - mnew));
+  if (log_on())
+    std::fprintf(stderr, "[mmdeig] extend L%d in %d new %d restarts %d steps %d\n", k, mi, mnew,
+                 restarts, L.j);
   // Schur (symmetric eig) of T, descending
   std::vector<double> T((size_t)mnew * mnew);
   for (int i = 0; i < mnew; ++i)
@@ -631,12 +684,15 @@ void Solver::refine(int k, double*& V, std::vector<double>& D, int& m, double ep
   double* Pd = pool_.d("rf:P", (size_t)ml * ml);
   double* Sd = pool_.d("rf:S", (size_t)ml * ml);
   double* work = pool_.d("gram:w", gram_work_size(n, ml, ml));
+  // on level 0 the solves run at 0.1 eps so the stop test lies above their noise
+  const double eps_solve = k == 0 ? 0.1 * eps : eps;
   // start block F = Q D + U G, g_i = cg(B, U^T M q_i, 0, eps)
   applyM(k, V, ml, MQ, ml, ml);
   if (nred > 0) {
     house_ut(H, MQ, ml, RB, ml, ml, s_);
     std::vector<int> it;
-    cg(k, OpKind::B, RB, ml, G, ml, nred, ml, eps, false, nullptr, 0, "bcg", st_ ? &it : nullptr);
+    cg(k, OpKind::B, RB, ml, G, ml, nred, ml, eps_solve, false, nullptr, 0, "bcg",
+       st_ ? &it : nullptr);
     if (st_) {
       st_->cg_B_calls[k] += ml;
       for (int x : it) st_->cg_B_iters[k] += x;
@@ -651,6 +707,7 @@ void Solver::refine(int k, double*& V, std::vector<double>& D, int& m, double ep
   bool have_prev = false;
   int mh = 0;
   const double thresh = eps / std::sqrt(lam_max_M);
+  std::vector<double> hist;
   std::vector<double> Sh((size_t)ml * ml), w, Z, Ph((size_t)ml * ml);
   int it = 0;
   for (it = 1; it <= o_.max_refine; ++it) {
@@ -660,7 +717,7 @@ void Solver::refine(int k, double*& V, std::vector<double>& D, int& m, double ep
     h2d(Dd, mu_prev.data(), ml);
     scale_cols(Q, ml, Dd, F2, ml, n, ml, false, s_);
     std::vector<int> its;
-    pcg(k, W, ml, F2, ml, ml, eps, true, st_ ? &its : nullptr);
+    pcg(k, W, ml, F2, ml, ml, eps_solve, true, st_ ? &its : nullptr);
     if (st_) {
       st_->pcg_A_calls[k] += ml;
       for (int x : its) st_->pcg_A_iters[k] += x;
@@ -697,7 +754,14 @@ void Solver::refine(int k, double*& V, std::vector<double>& D, int& m, double ep
       sync();
       double fro = 0.0;
       for (double x : cnh) fro += x;
-      done = std::sqrt(fro) < thresh;
+      const double dist = std::sqrt(fro);
+      hist.push_back(dist);
+      // stop at the threshold, or at a stagnated floor below 10x the threshold
+      done = dist < thresh || (hist.size() > 5 && dist < 10 * thresh &&
+                               dist > 0.9 * hist[hist.size() - 6]);
+      if (log_on())
+        std::fprintf(stderr, "[mmdeig] refine L%d it %d ml %d mh %d dist %.3e thresh %.3e mu[0] %.6g mu[mh-1] %.6g mu[ml-1] %.6g\n",
+                     k, it, ml, mh, dist, thresh, Dn[0], Dn[std::max(mh - 1, 0)], Dn[ml - 1]);
     } else if (have_prev && mh == 0) {
       done = true;
     }

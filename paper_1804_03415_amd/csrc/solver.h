@@ -55,6 +55,8 @@ class Solver {
           const std::string& tag, std::vector<int>* iters);
   void pcg(int k, const double* B, int ldb, double* X, int ldx, int b, double tol, bool use_x0,
            std::vector<int>* iters);
+  bool pcg_single(int k, const double* B, double* X, double tol, bool use_x0,
+                  std::vector<int>* iters);
 
   // Lanczos / extension / refinement
   struct Lanczos;
@@ -92,6 +94,7 @@ class Solver {
   HBuf<double> hd_;
   HBuf<int> hi_;
   int inner_iters_ = 16;
+  bool use_persistent_ = true;
   int cur_level_ = 0;
   int64_t draws_[MMD_MAX_LEVELS] = {};
 };

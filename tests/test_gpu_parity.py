@@ -110,10 +110,11 @@ def test_level_operators(built, torch_cuda):
             assert np.abs(Y - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
-def test_level_solves(built, torch_cuda):
+@pytest.mark.parametrize("b", [1, 4])
+def test_level_solves(built, torch_cuda, b):
+    """b = 1 runs the persistent single-vector kernel, b = 4 the block kernels."""
     torch = torch_cuda
     p, kw, dec, M = built
-    b = 4
     tol = 1e-10
     for k in range(0, M.K + 1):
         lev = M.levels[k]
@@ -138,7 +139,7 @@ def test_level_solves(built, torch_cuda):
             up = M.levels[k + 1]
             U = up.U_apply(np.eye(up.nb()))
             B = U.T @ Ad @ U
-            r2 = wl.random_block(up.nb(), b, seed=40 + k)
+            r2 = wl.random_block(up.nb(), max(b, 2), seed=40 + k)
             G, it = dec.solve(k, 1, _t(torch, r2), tol=tol)
             G = G.cpu().numpy()
             nb2 = np.linalg.norm(r2, axis=0)
