@@ -95,6 +95,20 @@ typedef struct {
   int64_t missed_swaps;
   double seconds_level[MMD_MAX_LEVELS];
   double seconds_total;
+  /* wall time by phase, summed over levels: 0 refinement block PCG, 1 refinement
+     B-CG, 2 refinement host dense work, 3 refinement QR/Gram/rotations,
+     4 extension OP (PCG), 5 extension re-orthogonalisation, 6 restarts,
+     7 output step and multiplicity check */
+  double seconds_phase[8];
+  /* the level-0 SpMM of the refinement block PCG (the dominant HBM kernel),
+     timed with HIP events on the solve's stream: launches, summed duration in
+     milliseconds, summed algorithmic bytes (matrix once, each block read or
+     written once) and the block width of the last launch */
+  int64_t spmm0_launches;
+  double spmm0_ms;
+  double spmm0_bytes;
+  int32_t spmm0_b;
+  int32_t reserved_stats;
 } eig_stats;
 
 typedef struct mmd_handle mmd_handle;

@@ -58,12 +58,21 @@ class eig_stats(ctypes.Structure):
                 ("ext_in", ctypes.c_int64 * _L), ("ext_out", ctypes.c_int64 * _L),
                 ("lanczos_steps", ctypes.c_int64 * _L), ("restarts", ctypes.c_int64 * _L),
                 ("missed_swaps", ctypes.c_int64), ("seconds_level", ctypes.c_double * _L),
-                ("seconds_total", ctypes.c_double)]
+                ("seconds_total", ctypes.c_double), ("seconds_phase", ctypes.c_double * 8),
+                ("spmm0_launches", ctypes.c_int64), ("spmm0_ms", ctypes.c_double),
+                ("spmm0_bytes", ctypes.c_double), ("spmm0_b", ctypes.c_int32),
+                ("reserved_stats", ctypes.c_int32)]
+
+    PHASES = ("refine_pcg", "refine_bcg", "refine_host_dense", "refine_qr_gram", "extend_op",
+              "extend_orth", "restart", "output")
 
     def as_dict(self):
         K = self.K
         out = {"K": K, "nconv": self.nconv, "missed_swaps": self.missed_swaps,
-               "seconds_total": self.seconds_total, "levels": {}}
+               "seconds_total": self.seconds_total, "levels": {},
+               "phases": {n: round(self.seconds_phase[i], 4) for i, n in enumerate(self.PHASES)},
+               "spmm0": {"launches": self.spmm0_launches, "ms": self.spmm0_ms,
+                         "bytes": self.spmm0_bytes, "b": self.spmm0_b}}
         for k in range(K + 1):
             out["levels"][k] = {f: getattr(self, f)[k] for f in (
                 "ref_in", "ref_out", "ref_iter", "cg_B_calls", "cg_B_iters", "pcg_A_calls",

@@ -85,7 +85,29 @@ int mmd_export(const mmd_handle* h, int32_t level, int32_t which, int64_t* n_row
     MMD_REQUIRE(which >= 0 && which <= 2, MMD_EINVAL, "which must be 0, 1 or 2");
     MMD_REQUIRE(which == 0 || level >= 1, MMD_EINVAL, "M and Psi exist for levels >= 1");
     const mmd::LevelHost& L = h->host[level];
-    const mmd::HostCSR& X = which == 0 ? L.A : (which == 1 ? L.M : L.Psi);
+    const mmd::HostCSR* src = which == 0 ? &L.A : (which == 1 ? &L.M : &L.Psi);
+    mmd::HostCSR tmp;
+    if (!h->perm.empty() && level == 0 && which == 0) src = &h->A_user;
+    if (!h->perm.empty() && level == 1 && which == 2) {
+      // rows of Psi^(1) are level-0 dofs: return them in the caller's numbering
+      const mmd::HostCSR& P = L.Psi;
+      const int n = P.n_rows;
+      std::vector<int> iperm(n);
+      for (int i = 0; i < n; ++i) iperm[h->perm[i]] = i;
+      tmp.n_rows = P.n_rows;
+      tmp.n_cols = P.n_cols;
+      tmp.ptr.assign(n + 1, 0);
+      for (int u = 0; u < n; ++u) tmp.ptr[u + 1] = tmp.ptr[u] + (P.ptr[iperm[u] + 1] - P.ptr[iperm[u]]);
+      tmp.col.reserve(P.nnz());
+      tmp.val.reserve(P.nnz());
+      for (int u = 0; u < n; ++u)
+        for (int64_t q = P.ptr[iperm[u]]; q < P.ptr[iperm[u] + 1]; ++q) {
+          tmp.col.push_back(P.col[q]);
+          tmp.val.push_back(P.val[q]);
+        }
+      src = &tmp;
+    }
+    const mmd::HostCSR& X = *src;
     if (n_rows) *n_rows = X.n_rows;
     if (n_cols) *n_cols = X.n_cols;
     if (nnz) *nnz = X.nnz();

@@ -49,6 +49,11 @@ struct LevelDev {
 struct mmd_handle {
   int64_t n = 0;
   int K = 0;
+  // Level 0 is stored renumbered patch by patch (Morton order of the patches):
+  // internal index i holds caller index perm[i].  Empty: identity.
+  std::vector<int> perm;
+  mmd::DBuf<int> d_perm;
+  mmd::HostCSR A_user;  // the caller's matrix in its own numbering (export)
   std::vector<mmd::LevelHost> host;
   std::vector<mmd::LevelDev> dev;
   std::vector<double> eps;  // cumulative eps_k, eps[0] = 0

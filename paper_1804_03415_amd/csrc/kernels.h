@@ -115,12 +115,15 @@ void scale_vec_dev(const double* x, const double* scal, bool inv_sqrt, double* y
 // Y(:, idx[j]) gathered into Z(:, j)
 void gather_cols(const double* Y, int ldy, const int* idx, double* Z, int ldz, int n, int b,
                  hipStream_t s);
-// column-major output: out[c*n + i] = X[i*ldx + c] * colscale[c]
+// column-major output: out[c*n + perm[i]] = X[i*ldx + c] * colscale[c] (perm may be null)
 void to_colmajor(const double* X, int ldx, const double* colscale, double* out, int n, int b,
-                 hipStream_t s);
-// per column: index of largest |X(i,c)| (lowest index on ties) and the value
+                 const int* perm, hipStream_t s);
+// per column: the entry of largest |X(i,c)| (ties: lowest perm[i], or i when perm is null)
 void col_absmax(const double* X, int ldx, int n, int b, int* idx, double* val,
-                hipStream_t s);
+                const int* perm, hipStream_t s);
+// rows: gather Y[i] = X[idx[i]] or scatter Y[idx[i]] = X[i] (n rows, b columns)
+void permute_rows(const double* X, int ldx, double* Y, int ldy, int n, int b, const int* idx,
+                  bool scatter, hipStream_t s);
 
 // int64 -> int32 copy of caller row pointers (the caller checks nnz < 2^31)
 void i64_to_i32(const int64_t* src, int* dst, int64_t n, hipStream_t s);

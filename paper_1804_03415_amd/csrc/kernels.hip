@@ -24,6 +24,14 @@ constexpr int kBlock = 256;
 
 inline int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
 
+// Workgroups are dealt to the 8 XCDs round-robin; renumber them so the blocks
+// of one XCD cover a contiguous range of rows and share that XCD's L2.
+__device__ inline int xcd_block(int bx, int gx) {
+  constexpr int kXcd = 8;
+  if (gx % kXcd) return bx;
+  return (bx % kXcd) * (gx / kXcd) + bx / kXcd;
+}
+
 inline void check_launch() {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) throw Error(MMD_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -56,14 +64,27 @@ __global__ __launch_bounds__(kBlock) void k_spmm(
   const double bt = (FUSE && cok && !first) ? beta[colx] : 0.0;
   double dsum = 0.0;
   const int groups = (n_rows + R - 1) / R;
-  for (int g = blockIdx.x * WPB + wid; g < groups; g += gridDim.x * WPB) {
+  const int bx = xcd_block(blockIdx.x, gridDim.x);
+  for (int g = bx * WPB + wid; g < groups; g += gridDim.x * WPB) {
     const int row = g * R + r;
     double acc = 0.0;
     double xi = 0.0;
     if (row < n_rows && cok) {
       const int lo = rowptr[row], hi = rowptr[row + 1];
       if (EDGE) xi = X[(size_t)row * ldx + colx];
-      for (int k = lo + s; k < hi; k += LPR) {
+      int k = lo + s;
+      // four gathers in flight per lane
+      for (; k + 3 * LPR < hi; k += 4 * LPR) {
+        const int j0 = col[k], j1 = col[k + LPR], j2 = col[k + 2 * LPR], j3 = col[k + 3 * LPR];
+        const double v0 = val[k], v1 = val[k + LPR], v2 = val[k + 2 * LPR], v3 = val[k + 3 * LPR];
+        const double x0 = X[(size_t)j0 * ldx + colx], x1 = X[(size_t)j1 * ldx + colx];
+        const double x2 = X[(size_t)j2 * ldx + colx], x3 = X[(size_t)j3 * ldx + colx];
+        if (EDGE)
+          acc += v0 * (xi - x0) + v1 * (xi - x1) + v2 * (xi - x2) + v3 * (xi - x3);
+        else
+          acc += v0 * x0 + v1 * x1 + v2 * x2 + v3 * x3;
+      }
+      for (; k < hi; k += LPR) {
         const double xj = X[(size_t)col[k] * ldx + colx];
         if (EDGE)
           acc += val[k] * (xi - xj);
@@ -75,7 +96,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm(
     for (int off = CT; off < CT * LPR; off <<= 1) acc += __shfl_xor(acc, off, kWave);
     if (s == 0 && row < n_rows && cok) {
       double y = EDGE ? diag[row] * xi + acc : acc;
-      if (FUSE) {
+      if (FUSE) {  // partial == nullptr: direction update only, p.q taken separately
         const size_t iy = (size_t)row * ldy + colx;
         const size_t ip = (size_t)row * ldp + colx;
         double pn;
@@ -93,7 +114,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm(
       Y[(size_t)row * ldy + colx] = y;
     }
   }
-  if (FUSE || DOT) {
+  if ((FUSE && partial != nullptr) || DOT) {
     // lanes with s == 0 hold (r, c) partial sums; combine over r and waves
     if (s == 0) red[(wid * R + r) * CT + c] = dsum;
     __syncthreads();
@@ -114,9 +135,11 @@ int launch_spmm_t(const CsrView& A, const double* X, int ldx, double* Y, int ldy
   constexpr int WPB = kBlock / kWave;
   const int groups = ceil_div(A.n_rows, R);
   int gx = ceil_div(groups, WPB);
-  const bool red = fuse || dotw != nullptr;
+  const bool red = (fuse && partial != nullptr) || dotw != nullptr;
   if (red) gx = std::min(gx, kRedBlocks);
   gx = std::max(gx, 1);
+  if (gx >= 8) gx = (gx + 7) / 8 * 8;  // whole XCD rounds (see xcd_block)
+  if (red) gx = std::min(gx, kRedBlocks);
   dim3 grid(gx, ceil_div(b, CT));
   const bool edge = A.diag != nullptr;
 #define MMD_SPMM_CASE(E, F, D)                                                             \
@@ -182,9 +205,19 @@ struct ColMap {
   bool act;
 };
 
+// blockDim.x == kBlock for b <= 256; for 256 < b <= 1024 the block has one
+// thread per column (rounded up to a wave) and walks rows one at a time.
 __device__ inline ColMap colmap(int b, int tile_c0) {
   ColMap m;
   m.b = b;
+  if (b > kBlock && (int)blockDim.x >= b) {
+    m.tb = blockDim.x;
+    m.rstep = 1;
+    m.col = threadIdx.x;
+    m.roff = 0;
+    m.act = threadIdx.x < b;
+    return m;
+  }
   if (b <= kBlock) {
     m.tb = (kBlock / b) * b;
     m.rstep = kBlock / b;
@@ -203,6 +236,10 @@ __device__ inline ColMap colmap(int b, int tile_c0) {
 
 __device__ inline void block_col_store(double v, const ColMap& m, double* partial) {
   __shared__ double sh[kBlock];
+  if (m.b > kBlock) {  // one thread per column: no block reduction needed
+    if (m.act) partial[(size_t)blockIdx.x * m.b + m.col] = v;
+    return;
+  }
   sh[threadIdx.x] = m.act ? v : 0.0;
   __syncthreads();
   if (m.b <= kBlock) {
@@ -218,12 +255,12 @@ __device__ inline void block_col_store(double v, const ColMap& m, double* partia
 }
 
 template <int MODE>  // 0: X.*Y ; 1: two dots X.*Y1, X.*Y2
-__global__ __launch_bounds__(kBlock) void k_coldot(const double* __restrict__ X, int ldx,
+__global__ __launch_bounds__(1024) void k_coldot(const double* __restrict__ X, int ldx,
                                                    const double* __restrict__ Y1,
                                                    const double* __restrict__ Y2, int ldy,
                                                    int n, int b, double* __restrict__ p1,
                                                    double* __restrict__ p2) {
-  const int ntile = b <= kBlock ? 1 : (b + kBlock - 1) / kBlock;
+  const int ntile = (b <= kBlock || (int)blockDim.x >= b) ? 1 : (b + kBlock - 1) / kBlock;
   for (int tile = 0; tile < ntile; ++tile) {
     ColMap m = colmap(b, tile * kBlock);
     double a1 = 0.0, a2 = 0.0;
@@ -337,14 +374,14 @@ __global__ void k_pcg_beta(ColScalars sc, const double* __restrict__ prz,
 }
 
 // ------------------------------------------------------------------ elementwise
-__global__ __launch_bounds__(kBlock) void k_cg_update(double* __restrict__ X, int ldx,
+__global__ __launch_bounds__(1024) void k_cg_update(double* __restrict__ X, int ldx,
                                                       double* __restrict__ R,
                                                       const double* __restrict__ P,
                                                       const double* __restrict__ Q, int ld,
                                                       int n, int b,
                                                       const double* __restrict__ alpha,
                                                       double* __restrict__ partial) {
-  const int ntile = b <= kBlock ? 1 : (b + kBlock - 1) / kBlock;
+  const int ntile = (b <= kBlock || (int)blockDim.x >= b) ? 1 : (b + kBlock - 1) / kBlock;
   for (int tile = 0; tile < ntile; ++tile) {
     ColMap m = colmap(b, tile * kBlock);
     double acc = 0.0;
@@ -436,15 +473,28 @@ __global__ void k_gather_cols(const double* __restrict__ Y, int ldy, const int* 
 
 __global__ void k_to_colmajor(const double* __restrict__ X, int ldx,
                               const double* __restrict__ scale, double* __restrict__ out, int n,
-                              int b) {
+                              int b, const int* __restrict__ perm) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)n * b) return;
   const int64_t c = t / n, i = t % n;
-  out[c * n + i] = X[i * ldx + c] * scale[c];
+  const int64_t o = perm ? perm[i] : i;
+  out[c * n + o] = X[i * ldx + c] * scale[c];
+}
+
+__global__ void k_permute_rows(const double* __restrict__ X, int ldx, double* __restrict__ Y,
+                               int ldy, int n, int b, const int* __restrict__ idx, int scatter) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * b) return;
+  const int64_t i = t / b, c = t % b;
+  if (scatter)
+    Y[(int64_t)idx[i] * ldy + c] = X[i * ldx + c];
+  else
+    Y[i * ldy + c] = X[(int64_t)idx[i] * ldx + c];
 }
 
 __global__ void k_absmax_part(const double* __restrict__ X, int ldx, int n, int b, int chunk,
-                              int* __restrict__ pidx, double* __restrict__ pval) {
+                              int* __restrict__ pidx, double* __restrict__ pval,
+                              const int* __restrict__ perm) {
   const int c = blockIdx.y * blockDim.x + threadIdx.x;
   if (c >= b) return;
   const int lo = blockIdx.x * chunk;
@@ -453,10 +503,11 @@ __global__ void k_absmax_part(const double* __restrict__ X, int ldx, int n, int 
   int bi = n;
   for (int i = lo; i < hi; ++i) {
     const double v = X[(size_t)i * ldx + c];
-    if (fabs(v) > best) {
+    const int ui = perm ? perm[i] : i;
+    if (fabs(v) > best || (fabs(v) == best && ui < bi)) {
       best = fabs(v);
       bv = v;
-      bi = i;
+      bi = ui;
     }
   }
   pidx[(size_t)blockIdx.x * b + c] = bi;
@@ -468,13 +519,14 @@ __global__ void k_absmax_fin(const int* __restrict__ pidx, const double* __restr
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= b) return;
   double best = -1.0, bv = 0.0;
-  int bi = 0;
+  int bi = 0x7fffffff;
   for (int q = 0; q < nch; ++q) {
     const double v = pval[(size_t)q * b + c];
-    if (fabs(v) > best) {  // chunks in ascending row order: ties keep the lower index
+    const int ui = pidx[(size_t)q * b + c];
+    if (fabs(v) > best || (fabs(v) == best && ui < bi)) {  // ties: lowest caller index
       best = fabs(v);
       bv = v;
-      bi = pidx[(size_t)q * b + c];
+      bi = ui;
     }
   }
   idx[c] = bi;
@@ -614,6 +666,12 @@ __global__ __launch_bounds__(kBlock) void k_gemv_n_sub(const double* __restrict_
   if (lane == 0) z[row] -= acc;
 }
 
+// threads per block of the column-reduction kernels (see colmap)
+inline int red_threads(int b) {
+  if (b > kBlock && b <= 1024) return (b + kWave - 1) / kWave * kWave;
+  return kBlock;
+}
+
 inline int red_grid(int n, int b) {
   const int rows_per_block = b <= kBlock ? kBlock / b : 1;
   const int want = ceil_div((int64_t)n, (int64_t)rows_per_block * 8);
@@ -660,7 +718,7 @@ void house_u(const HouseView& H, const double* y, int ldy, double* x, int ldx, i
 int col_dot(const double* X, int ldx, const double* Y, int ldy, int n, int b, double* partial,
             hipStream_t s) {
   const int g = red_grid(n, b);
-  hipLaunchKernelGGL(k_coldot<0>, dim3(g), dim3(kBlock), 0, s, X, ldx, Y, nullptr, ldy, n, b,
+  hipLaunchKernelGGL(k_coldot<0>, dim3(g), dim3(red_threads(b)), 0, s, X, ldx, Y, nullptr, ldy, n, b,
                      partial, nullptr);
   check_launch();
   return g;
@@ -669,7 +727,7 @@ int col_dot(const double* X, int ldx, const double* Y, int ldy, int n, int b, do
 int col_dot2(const double* X, int ldx, const double* Y1, const double* Y2, int ldy, int n,
              int b, double* partial1, double* partial2, hipStream_t s) {
   const int g = red_grid(n, b);
-  hipLaunchKernelGGL(k_coldot<1>, dim3(g), dim3(kBlock), 0, s, X, ldx, Y1, Y2, ldy, n, b,
+  hipLaunchKernelGGL(k_coldot<1>, dim3(g), dim3(red_threads(b)), 0, s, X, ldx, Y1, Y2, ldy, n, b,
                      partial1, partial2);
   check_launch();
   return g;
@@ -716,7 +774,7 @@ void pcg_beta(ColScalars sc, const double* part_rz, const double* part_rzo, int 
 int cg_update(double* X, int ldx, double* R, const double* P, const double* Q, int ld, int n,
               int b, const double* alpha, double* partial, hipStream_t s) {
   const int g = red_grid(n, b);
-  hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(kBlock), 0, s, X, ldx, R, P, Q, ld, n, b, alpha,
+  hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(red_threads(b)), 0, s, X, ldx, R, P, Q, ld, n, b, alpha,
                      partial);
   check_launch();
   return g;
@@ -783,14 +841,23 @@ void gather_cols(const double* Y, int ldy, const int* idx, double* Z, int ldz, i
 }
 
 void to_colmajor(const double* X, int ldx, const double* colscale, double* out, int n, int b,
-                 hipStream_t s) {
+                 const int* perm, hipStream_t s) {
   if ((int64_t)n * b == 0) return;
   hipLaunchKernelGGL(k_to_colmajor, dim3(ew_grid((int64_t)n * b)), dim3(kBlock), 0, s, X, ldx,
-                     colscale, out, n, b);
+                     colscale, out, n, b, perm);
   check_launch();
 }
 
-void col_absmax(const double* X, int ldx, int n, int b, int* idx, double* val, hipStream_t s) {
+void permute_rows(const double* X, int ldx, double* Y, int ldy, int n, int b, const int* idx,
+                  bool scatter, hipStream_t s) {
+  if ((int64_t)n * b == 0) return;
+  hipLaunchKernelGGL(k_permute_rows, dim3(ew_grid((int64_t)n * b)), dim3(kBlock), 0, s, X, ldx,
+                     Y, ldy, n, b, idx, scatter ? 1 : 0);
+  check_launch();
+}
+
+void col_absmax(const double* X, int ldx, int n, int b, int* idx, double* val, const int* perm,
+                hipStream_t s) {
   // partial results live in the tail of the output-sized scratch the caller owns
   static thread_local DBuf<int> pidx;
   static thread_local DBuf<double> pval;
@@ -799,7 +866,7 @@ void col_absmax(const double* X, int ldx, int n, int b, int* idx, double* val, h
   pidx.ensure((size_t)nch * b);
   pval.ensure((size_t)nch * b);
   hipLaunchKernelGGL(k_absmax_part, dim3(nch, ceil_div(b, kBlock)), dim3(kBlock), 0, s, X, ldx,
-                     n, b, chunk, pidx.p, pval.p);
+                     n, b, chunk, pidx.p, pval.p, perm);
   check_launch();
   hipLaunchKernelGGL(k_absmax_fin, dim3(ceil_div(b, kBlock)), dim3(kBlock), 0, s, pidx.p,
                      pval.p, nch, b, idx, val);

@@ -503,6 +503,53 @@ HostCSR psi_localized(const HostCSR& A, const Patches& P, const std::vector<doub
 
 }  // namespace
 
+// Renumber level 0 patch-major: patches in id order, members ascending.  The
+// SpMM gathers of level 0 then touch nearby rows (L2 reuse) and every patch
+// is a contiguous index range.  The first-level patches are rewritten in the
+// new numbering; the caller's numbering is restored at the API boundary.
+void renumber_level0(mmd_handle& h, Patches& P) {
+  LevelHost& L0 = h.host[0];
+  const int n = L0.n;
+  std::vector<int> perm;
+  perm.reserve(n);
+  for (auto& m : P) perm.insert(perm.end(), m.begin(), m.end());
+  std::vector<int> iperm(n);
+  for (int i = 0; i < n; ++i) iperm[perm[i]] = i;
+  h.A_user = L0.A;
+  HostCSR B;
+  B.n_rows = B.n_cols = n;
+  B.ptr.assign(n + 1, 0);
+  for (int i = 0; i < n; ++i) B.ptr[i + 1] = B.ptr[i] + (L0.A.ptr[perm[i] + 1] - L0.A.ptr[perm[i]]);
+  B.col.resize(L0.A.nnz());
+  B.val.resize(L0.A.nnz());
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int i = 0; i < n; ++i) {
+    const int o = perm[i];
+    std::vector<std::pair<int, double>> row;
+    for (int64_t q = L0.A.ptr[o]; q < L0.A.ptr[o + 1]; ++q) row.emplace_back(iperm[L0.A.col[q]], L0.A.val[q]);
+    std::sort(row.begin(), row.end());
+    for (size_t t = 0; t < row.size(); ++t) {
+      B.col[B.ptr[i] + t] = row[t].first;
+      B.val[B.ptr[i] + t] = row[t].second;
+    }
+  }
+  std::vector<double> s(n);
+  for (int i = 0; i < n; ++i) s[i] = L0.s[perm[i]];
+  L0.A = std::move(B);
+  L0.s = std::move(s);
+  if (!L0.coords.empty()) {
+    std::vector<double> c(L0.coords.size());
+    for (int i = 0; i < n; ++i)
+      for (int a = 0; a < L0.cdim; ++a) c[(size_t)i * L0.cdim + a] = L0.coords[(size_t)perm[i] * L0.cdim + a];
+    L0.coords = std::move(c);
+  }
+  for (auto& m : P) {
+    for (int& v : m) v = iperm[v];
+    std::sort(m.begin(), m.end());
+  }
+  h.perm = std::move(perm);
+}
+
 // ======================================================================= build
 void build_hierarchy(mmd_handle& h, const mmd_csr& in, const mmd_build_opts& o) {
   const int levels = o.levels > 0 ? o.levels : (o.levels < 0 ? 0 : 3);
@@ -539,6 +586,8 @@ void build_hierarchy(mmd_handle& h, const mmd_csr& in, const mmd_build_opts& o) 
     L0.grid.assign(in.grid, in.grid + in.grid_dim);
   }
   h.eps.assign(1, 0.0);
+  h.perm.clear();
+  h.A_user = HostCSR();
 
   for (int k = 1; k <= levels; ++k) {
     const LevelHost& prev = h.host[k - 1];
@@ -554,6 +603,7 @@ void build_hierarchy(mmd_handle& h, const mmd_csr& in, const mmd_build_opts& o) 
     }
     const int np = static_cast<int>(P.size());
     if (np >= prev.n || np < min_coarse) break;
+    if (k == 1) renumber_level0(h, P);
 
     LevelHost L;
     L.n = np;
@@ -649,6 +699,7 @@ void upload_csr(const HostCSR& X, DBuf<int>& ptr, DBuf<int>& col, DBuf<double>& 
 void upload_hierarchy(mmd_handle& h, hipStream_t s) {
   h.dev.clear();
   h.dev.resize(h.host.size());
+  if (!h.perm.empty()) h.d_perm.upload(h.perm, s);
   // level 0: edge form (off-diagonal weights w = -a_ij and self-loops s)
   {
     const LevelHost& L0 = h.host[0];

@@ -14,6 +14,7 @@ struct Pcg1Args {
   double *r = nullptr, *z = nullptr, *zo = nullptr, *p = nullptr, *q = nullptr;
   double *ri = nullptr, *pi = nullptr, *qi = nullptr;  // inner CG work
   double* red = nullptr;  // pcg1_red_size() doubles
+  unsigned* bar = nullptr;  // one arrival counter (zeroed by pcg1 before the launch)
   double tol = 0.0, tol_in = 0.0;
   int maxit = 100000, maxit_in = 500, use_x0 = 0;
   int lpr_a = 8, lpr_m = 8;

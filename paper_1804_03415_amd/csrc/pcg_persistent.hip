@@ -5,14 +5,18 @@
 // several kernel boundaries, so the whole solve (outer PCG and the inner CG
 // on M) runs here in one cooperative launch with grid-wide barriers.
 //
-// Barrier discipline: every block executes exactly the same sequence of
-// grid.sync() calls.  Each loop decision (convergence, curvature check,
-// iteration caps) is taken from scalars that every block computes from the
-// same global partial sums in the same order, so all blocks agree.
-#include <hip/hip_cooperative_groups.h>
+// Barrier discipline: every block executes exactly the same sequence of grid
+// barriers.  Each loop decision (convergence, curvature check, iteration
+// caps) is taken from scalars that every block computes from the same global
+// partial sums in the same order, so all blocks agree.
+//
+// Cross-XCD synchronisation costs about 30 ns per arriving block on MI355X,
+// so the kernel runs few fat workgroups (1024 threads) with a single arrival
+// counter; the cooperative launch guarantees they are co-resident.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "common.h"
 #include "pcg_persistent.h"
@@ -21,17 +25,31 @@ namespace mmd {
 
 namespace {
 
-namespace cg = cooperative_groups;
-
-constexpr int kThreads = 256;
+constexpr int kThreads = 1024;
 constexpr int kWave = 64;
 
 struct Ctx {
-  cg::grid_group grid;
+  unsigned* bar;  // arrival counter, zero at launch
+  unsigned gen;   // barriers passed so far
   int nblk, blk, gtid, gsize, gwave, nwave, lane;
   double* red;   // two disjoint slots of 2*nblk partial sums
   int slot;
 };
+
+// Grid barrier: every block adds one arrival (release), then waits until all
+// gridDim.x arrivals of this generation are in (relaxed spin, acquire fence).
+__device__ inline void grid_barrier(Ctx& c) {
+  __syncthreads();
+  c.gen += 1;
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(c.bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned target = c.gen * (unsigned)gridDim.x;
+    while (__hip_atomic_load(c.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target)
+      __builtin_amdgcn_s_sleep(1);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
 
 // Sum of v over the block, result valid in every thread.
 __device__ inline double block_sum(double v, double* sh) {
@@ -54,7 +72,7 @@ __device__ inline double grid_sum(Ctx& c, double part, double* sh) {
   const double b = block_sum(part, sh);
   double* r = c.red + (size_t)c.slot * 2 * c.nblk;  // slot regions are disjoint
   if (threadIdx.x == 0) r[c.blk] = b;
-  c.grid.sync();
+  grid_barrier(c);
   double t = 0.0;
   for (int j = threadIdx.x; j < c.nblk; j += kThreads) t += r[j];
   const double s = block_sum(t, sh);
@@ -72,7 +90,7 @@ __device__ inline void grid_sum2(Ctx& c, double p1, double p2, double* sh, doubl
     r[c.blk] = b1;
     r[c.nblk + c.blk] = b2;
   }
-  c.grid.sync();
+  grid_barrier(c);
   double t1 = 0.0, t2 = 0.0;
   for (int j = threadIdx.x; j < c.nblk; j += kThreads) {
     t1 += r[j];
@@ -83,21 +101,50 @@ __device__ inline void grid_sum2(Ctx& c, double p1, double p2, double* sh, doubl
   c.slot ^= 1;
 }
 
-// Row value (A x)_row for LPR lanes per row; lane sub-index s.  Edge form when
-// diag != null: s_i x_i + sum_j w_ij (x_i - x_j).
-__device__ inline double row_apply(const CsrView& A, const double* __restrict__ x, int row,
-                                   int s, int lpr) {
-  double acc = 0.0;
-  const int lo = A.rowptr[row], hi = A.rowptr[row + 1];
-  if (A.diag) {
-    const double xi = x[row];
-    for (int k = lo + s; k < hi; k += lpr) acc += A.val[k] * (xi - x[A.col[k]]);
-  } else {
-    for (int k = lo + s; k < hi; k += lpr) acc += A.val[k] * x[A.col[k]];
+// Rows handled by one wave per pass: kUnroll row-groups of kWave / lpr rows,
+// their gathers interleaved so a wave keeps several loads in flight.
+constexpr int kUnroll = 4;
+
+// acc[u] = (A x)_row(u) for the kUnroll row-groups g0 + u * nwave of this wave
+// (edge form when A.diag != null: s_i x_i + sum_j w_ij (x_i - x_j)).  All lanes
+// of the wave call this together; lanes of rows past the end get zero.
+__device__ inline void rows_apply(const Ctx& c, const CsrView& A, const double* __restrict__ x,
+                                  int lpr, int g0, int groups, int row[kUnroll],
+                                  double acc[kUnroll]) {
+  const int R = kWave / lpr;
+  const int s = c.lane % lpr;
+  const int r = c.lane / lpr;
+  int lo[kUnroll], hi[kUnroll];
+  double xi[kUnroll];
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) {
+    const int g = g0 + u * c.nwave;
+    row[u] = g * R + r;
+    const bool ok = g < groups && row[u] < A.n_rows;
+    if (!ok) row[u] = -1;
+    lo[u] = ok ? A.rowptr[row[u]] + s : 0;
+    hi[u] = ok ? A.rowptr[row[u] + 1] : 0;
+    xi[u] = (ok && A.diag) ? x[row[u]] : 0.0;
+    acc[u] = 0.0;
   }
-  for (int off = 1; off < lpr; off <<= 1) acc += __shfl_xor(acc, off, kWave);
-  if (A.diag) acc += A.diag[row] * x[row];
-  return acc;
+  for (int t = 0;; t += lpr) {
+    bool any = false;
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int k = lo[u] + t;
+      if (k < hi[u]) {
+        any = true;
+        const double xj = x[A.col[k]];
+        acc[u] += A.diag ? A.val[k] * (xi[u] - xj) : A.val[k] * xj;
+      }
+    }
+    if (!any) break;
+  }
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) {
+    for (int off = 1; off < lpr; off <<= 1) acc[u] += __shfl_xor(acc[u], off, kWave);
+    if (A.diag && row[u] >= 0) acc[u] += A.diag[row[u]] * xi[u];
+  }
 }
 
 // Fused CG direction step: w = A rr (all rows of rr complete), then per row
@@ -106,20 +153,22 @@ __device__ inline double dir_step(Ctx& c, const CsrView& A, int lpr, const doubl
                                   double* q, double beta, bool first) {
   const int R = kWave / lpr;
   const int s = c.lane % lpr;
-  const int r = c.lane / lpr;
   const int groups = (A.n_rows + R - 1) / R;
   double part = 0.0;
-  for (int g = c.gwave; g < groups; g += c.nwave) {
-    const int row = g * R + r;
-    // all lanes of a row-group are inside the loop together (uniform trip count)
-    double w = 0.0;
-    if (row < A.n_rows) w = row_apply(A, rr, row, s, lpr);
-    if (row < A.n_rows && s == 0) {
-      const double pn = first ? rr[row] : rr[row] + beta * p[row];
-      const double qn = first ? w : w + beta * q[row];
-      p[row] = pn;
-      q[row] = qn;
-      part += pn * qn;
+  for (int g0 = c.gwave; g0 < groups; g0 += kUnroll * c.nwave) {
+    int row[kUnroll];
+    double w[kUnroll];
+    rows_apply(c, A, rr, lpr, g0, groups, row, w);
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (row[u] >= 0 && s == 0) {
+        const int i = row[u];
+        const double pn = first ? rr[i] : rr[i] + beta * p[i];
+        const double qn = first ? w[u] : w[u] + beta * q[i];
+        p[i] = pn;
+        q[i] = qn;
+        part += pn * qn;
+      }
     }
   }
   return part;
@@ -127,26 +176,31 @@ __device__ inline double dir_step(Ctx& c, const CsrView& A, int lpr, const doubl
 
 __global__ __launch_bounds__(kThreads) void k_pcg1(Pcg1Args a) {
   __shared__ double sh[kThreads / kWave];
-  Ctx c{cg::this_grid(), (int)gridDim.x, (int)blockIdx.x,
-        (int)(blockIdx.x * blockDim.x + threadIdx.x), (int)(gridDim.x * blockDim.x),
-        (int)((blockIdx.x * blockDim.x + threadIdx.x) / kWave),
+  // rows are dealt per XCD-contiguous block number (workgroups go round-robin to XCDs)
+  const int bx = (gridDim.x % 8) ? (int)blockIdx.x
+                                 : (int)((blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8);
+  Ctx c{a.bar, 0u, (int)gridDim.x, (int)blockIdx.x,
+        (int)(bx * blockDim.x + threadIdx.x), (int)(gridDim.x * blockDim.x),
+        (int)((bx * blockDim.x + threadIdx.x) / kWave),
         (int)((gridDim.x * blockDim.x) / kWave), (int)(threadIdx.x & (kWave - 1)), a.red, 0};
   const int n = a.n;
   const bool pre = a.M.rowptr != nullptr;
   // r = b - A x0 (or b with x = 0); ||b||^2, ||r||^2
   double pb = 0.0, pr = 0.0;
   if (a.use_x0) {
-    // w stored in q temporarily
+    // w = A x0 stored in q temporarily
     const int R = kWave / a.lpr_a;
-    const int s = c.lane % a.lpr_a, rr = c.lane / a.lpr_a;
+    const int s = c.lane % a.lpr_a;
     const int groups = (n + R - 1) / R;
-    for (int g = c.gwave; g < groups; g += c.nwave) {
-      const int row = g * R + rr;
-      double w = 0.0;
-      if (row < n) w = row_apply(a.A, a.x, row, s, a.lpr_a);
-      if (row < n && s == 0) a.q[row] = w;
+    for (int g0 = c.gwave; g0 < groups; g0 += kUnroll * c.nwave) {
+      int row[kUnroll];
+      double w[kUnroll];
+      rows_apply(c, a.A, a.x, a.lpr_a, g0, groups, row, w);
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+        if (row[u] >= 0 && s == 0) a.q[row[u]] = w[u];
     }
-    c.grid.sync();
+    grid_barrier(c);
     for (int i = c.gtid; i < n; i += c.gsize) {
       const double ri = a.b[i] - a.q[i];
       a.r[i] = ri;
@@ -206,7 +260,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg1(Pcg1Args a) {
         a.z[i] = 0.0;
         a.ri[i] = a.r[i];
       }
-      c.grid.sync();
+      grid_barrier(c);
       double rri = rnorm2, bi = 0.0;
       bool f = true;
       int k = 0;
@@ -296,6 +350,7 @@ int lanes_for(double avg) {
 int pcg1_grid() {
   static int cached = 0;
   if (cached) return cached;
+  (void)0;
   int dev = 0;
   MMD_HIP(hipGetDevice(&dev));
   int coop = 0;
@@ -306,12 +361,19 @@ int pcg1_grid() {
   int per = 0;
   MMD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_pcg1, kThreads, 0));
   MMD_REQUIRE(per > 0, MMD_EHIP, "persistent PCG kernel cannot be resident");
-  cached = cus * std::min(per, 2);
+  cached = cus * per;  // upper bound for co-residency
   return cached;
 }
 
 void pcg1(Pcg1Args a, hipStream_t s) {
-  const int grid = std::min(pcg1_grid(), std::max(1, (a.n + kThreads - 1) / kThreads));
+  // blocks: barrier cost (~30 ns per block) against memory-level parallelism
+  const int64_t work = a.A.nnz + (a.M.rowptr ? a.M.nnz : 0);
+  int grid = static_cast<int>(std::min<int64_t>(128, std::max<int64_t>(16, work / 16384)));
+  if (const char* e = std::getenv("MMDEIG_COOP_BLOCKS")) grid = std::max(1, std::atoi(e));
+  grid = std::min(grid, pcg1_grid());
+  grid = std::min(grid, std::max(1, (a.n + kThreads - 1) / kThreads * 4));
+  if (grid >= 8) grid = grid / 8 * 8;  // whole XCD rounds
+  MMD_HIP(hipMemsetAsync(a.bar, 0, sizeof(unsigned), s));
   a.lpr_a = lanes_for(a.A.avg_row);
   a.lpr_m = a.M.rowptr ? lanes_for(a.M.avg_row) : 8;
   void* args[] = {&a};
@@ -319,6 +381,6 @@ void pcg1(Pcg1Args a, hipStream_t s) {
                                      dim3(kThreads), args, 0, s));
 }
 
-size_t pcg1_red_size() { return 4 * (size_t)4096; }
+size_t pcg1_red_size() { return 4 * (size_t)1024; }
 
 }  // namespace mmd

@@ -42,9 +42,11 @@ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
   }
 }
 
-// entry i of draw `call` at `level`: counter (i/2, call, level, 0), values in [-0.5, 0.5)
-void uniform_vector(std::vector<double>& v, int n, uint64_t seed, int level, int64_t call) {
-  v.resize(n);
+// Entry i of draw `call` at `level`: counter (i/2, call, level, 0), values in
+// [-0.5, 0.5).  With a renumbering, internal entry j is the caller's entry perm[j].
+void uniform_vector(std::vector<double>& v, int n, uint64_t seed, int level, int64_t call,
+                    const std::vector<int>* perm) {
+  std::vector<double> u(n + 1);
   const double inv53 = 1.0 / 9007199254740992.0;
   for (int c = 0; 2 * c < n; ++c) {
     uint32_t ctr[4] = {static_cast<uint32_t>(c), static_cast<uint32_t>(call),
@@ -52,9 +54,11 @@ void uniform_vector(std::vector<double>& v, int n, uint64_t seed, int level, int
     philox4x32_10(ctr, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
     const double a = (static_cast<double>(ctr[0] >> 5) * 67108864.0 + static_cast<double>(ctr[1] >> 6)) * inv53;
     const double b = (static_cast<double>(ctr[2] >> 5) * 67108864.0 + static_cast<double>(ctr[3] >> 6)) * inv53;
-    v[2 * c] = a - 0.5;
-    if (2 * c + 1 < n) v[2 * c + 1] = b - 0.5;
+    u[2 * c] = a - 0.5;
+    u[2 * c + 1] = b - 0.5;
   }
+  v.resize(n);
+  for (int j = 0; j < n; ++j) v[j] = perm ? u[(*perm)[j]] : u[j];
 }
 
 ColScalars make_scalars(Pool& pool, const std::string& tag, int b) {
@@ -97,6 +101,27 @@ int keep_count(const std::vector<double>& D, int ml, double mu_h, double gamma) 
   return mh;
 }
 
+// Wall-clock phase timer; syncs the stream at both ends only when stats are on.
+struct PhaseTimer {
+  eig_stats* st;
+  int phase;
+  hipStream_t s;
+  std::chrono::steady_clock::time_point t0;
+  PhaseTimer(eig_stats* st_, int ph, hipStream_t s_) : st(st_), phase(ph), s(s_) {
+    if (st) {
+      (void)hipStreamSynchronize(s);
+      t0 = std::chrono::steady_clock::now();
+    }
+  }
+  ~PhaseTimer() {
+    if (st) {
+      (void)hipStreamSynchronize(s);
+      st->seconds_phase[phase] +=
+          std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+  }
+};
+
 }  // namespace
 
 struct Solver::Lanczos {
@@ -125,6 +150,59 @@ Solver::Solver(mmd_handle& h, hipStream_t s, const eig_opts& o, eig_stats* st)
   if (o_.max_refine <= 0) o_.max_refine = 200;
   hd_.ensure(4096);
   hi_.ensure(4096);
+}
+
+Solver::~Solver() {
+  for (auto& pr : ev_pending_) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  for (auto e : ev_free_) (void)hipEventDestroy(e);
+  if (ev_open_) (void)hipEventDestroy(ev_open_);
+}
+
+void Solver::spmm0_begin() {
+  if (!st_) return;
+  hipEvent_t e;
+  if (ev_free_.empty()) {
+    MMD_HIP(hipEventCreate(&e));
+  } else {
+    e = ev_free_.back();
+    ev_free_.pop_back();
+  }
+  MMD_HIP(hipEventRecord(e, s_));
+  ev_open_ = e;
+}
+
+void Solver::spmm0_end(double bytes, int b) {
+  if (!st_ || !ev_open_) return;
+  hipEvent_t e;
+  if (ev_free_.empty()) {
+    MMD_HIP(hipEventCreate(&e));
+  } else {
+    e = ev_free_.back();
+    ev_free_.pop_back();
+  }
+  MMD_HIP(hipEventRecord(e, s_));
+  ev_pending_.emplace_back(ev_open_, e);
+  ev_bytes_.push_back(bytes);
+  ev_open_ = nullptr;
+  st_->spmm0_b = b;
+}
+
+void Solver::harvest_timers() {
+  if (!st_) return;
+  for (size_t i = 0; i < ev_pending_.size(); ++i) {
+    float ms = 0.f;
+    MMD_HIP(hipEventElapsedTime(&ms, ev_pending_[i].first, ev_pending_[i].second));
+    st_->spmm0_ms += ms;
+    st_->spmm0_bytes += ev_bytes_[i];
+    st_->spmm0_launches += 1;
+    ev_free_.push_back(ev_pending_[i].first);
+    ev_free_.push_back(ev_pending_[i].second);
+  }
+  ev_pending_.clear();
+  ev_bytes_.clear();
 }
 
 // ------------------------------------------------------------------ operators
@@ -180,8 +258,22 @@ void Solver::cg(int k, OpKind op, const double* B, int ldb, double* X, int ldx, 
   MMD_HIP(hipMemsetAsync(sc.notspd, 0, sizeof(int), s_));
   auto iterate = [&](bool first) {
     int np;
-    if (csr) {
+    if (csr && b <= 32) {
       np = spmm(*csr, R, b, Q, b, b, s_, true, first, sc.beta, P, b, p1);
+    } else if (csr) {
+      // wide blocks: direction update over the full grid, p.q as a separate reduction
+      const bool timed = k == 0 && op == OpKind::A;
+      if (timed) spmm0_begin();
+      spmm(*csr, R, b, Q, b, b, s_, true, first, sc.beta, P, b, nullptr);
+      if (timed) {
+        // matrix once (weights + columns, row pointers, self-loops), R read once,
+        // P and Q read and written once
+        const double nnz = static_cast<double>(csr->nnz);
+        const double bytes = 12.0 * nnz + 12.0 * n + 40.0 * n * static_cast<double>(b) +
+                             (first ? -16.0 * n * static_cast<double>(b) : 0.0);
+        spmm0_end(bytes, b);
+      }
+      np = col_dot(P, b, Q, b, n, b, p1, s_);
     } else {
       xpay(R, b, P, b, n, b, sc.beta, first, s_);
       apply(P, b, Q, b);
@@ -241,6 +333,7 @@ bool Solver::pcg_single(int k, const double* B, double* X, double tol, bool use_
   a.pi = pool_.d("p1:pi", n);
   a.qi = pool_.d("p1:qi", n);
   a.red = pool_.d("p1:red", pcg1_red_size());
+  a.bar = reinterpret_cast<unsigned*>(pool_.i("p1:bar", 64));
   a.tol = tol;
   a.tol_in = 0.1 * tol;
   a.use_x0 = use_x0 ? 1 : 0;
@@ -305,7 +398,13 @@ void Solver::pcg(int k, const double* B, int ldb, double* X, int ldx, int b, dou
   int64_t inner_total = 0;
   while (true) {
     for (int t = 0; t < chunk; ++t) {
-      const int np = spmm(h_.dev[k].A, Z, b, Q, b, b, s_, true, first, sc.beta, P, b, p1);
+      int np;
+      if (b <= 32) {
+        np = spmm(h_.dev[k].A, Z, b, Q, b, b, s_, true, first, sc.beta, P, b, p1);
+      } else {
+        spmm(h_.dev[k].A, Z, b, Q, b, b, s_, true, first, sc.beta, P, b, nullptr);
+        np = col_dot(P, b, Q, b, n, b, p1, s_);
+      }
       cg_alpha(sc, p1, np, b, s_);
       const int nu = cg_update(X, ldx, R, P, Q, b, n, b, sc.alpha, p2, s_);
       pcg_conv(sc, p2, nu, b, s_);
@@ -392,7 +491,8 @@ void Solver::lanczos_orth(Lanczos& L, double* w, int jcols, std::vector<double>*
 
 void Solver::lanczos_random(Lanczos& L, double* out) {
   std::vector<double> v;
-  uniform_vector(v, L.n, o_.seed, L.k, draws_[L.k]++);
+  uniform_vector(v, L.n, o_.seed, L.k, draws_[L.k]++,
+                 (L.k == 0 && !h_.perm.empty()) ? &h_.perm : nullptr);
   h2d(out, v.data(), L.n);
   lanczos_orth(L, out, L.j, nullptr);
   sync();  // v goes out of scope
@@ -442,17 +542,23 @@ void Solver::lanczos_steps(Lanczos& L, int nsteps) {
     if (L.k == 0) copy_block(v, 1, rhs, 1, n, 1, s_);
     else applyM(L.k, v, 1, rhs, 1, 1);
     std::vector<int> it;
-    pcg(L.k, rhs, 1, L.w, 1, 1, L.eps_op, false, st_ ? &it : nullptr);
+    {
+      PhaseTimer pt(st_, 4, s_);
+      pcg(L.k, rhs, 1, L.w, 1, 1, L.eps_op, false, st_ ? &it : nullptr);
+    }
     if (st_) {
       st_->pcg_A_calls[L.k] += 1;
       st_->pcg_A_iters[L.k] += it.empty() ? 0 : it[0];
     }
-    L.wnorm = std::sqrt(mnorm2(L.k, L.w));
-    std::vector<double> hl;
-    lanczos_orth(L, L.w, j + 1, &hl);
-    L.T[(size_t)j * L.cap + j] = hl[0];
-    std::swap(L.f, L.w);
-    L.beta_f = std::sqrt(mnorm2(L.k, L.f));
+    {
+      PhaseTimer pt(st_, 5, s_);
+      L.wnorm = std::sqrt(mnorm2(L.k, L.w));
+      std::vector<double> hl;
+      lanczos_orth(L, L.w, j + 1, &hl);
+      L.T[(size_t)j * L.cap + j] = hl[0];
+      std::swap(L.f, L.w);
+      L.beta_f = std::sqrt(mnorm2(L.k, L.f));
+    }
     L.j = j + 1;
     if (st_) st_->lanczos_steps[L.k] += 1;
   }
@@ -475,6 +581,7 @@ bool Solver::ritz_converged(Lanczos& L, int nwant, double eps, bool relative) {
 }
 
 void Solver::restart(Lanczos& L, int kkeep, int p) {
+  PhaseTimer pt(st_, 6, s_);
   const int m = L.j;
   MMD_REQUIRE(m == kkeep + p, MMD_EINVAL, "restart size mismatch");
   std::vector<double> T((size_t)m * m);
@@ -690,6 +797,7 @@ void Solver::refine(int k, double*& V, std::vector<double>& D, int& m, double ep
   applyM(k, V, ml, MQ, ml, ml);
   if (nred > 0) {
     house_ut(H, MQ, ml, RB, ml, ml, s_);
+    PhaseTimer pt(st_, 1, s_);
     std::vector<int> it;
     cg(k, OpKind::B, RB, ml, G, ml, nred, ml, eps_solve, false, nullptr, 0, "bcg",
        st_ ? &it : nullptr);
@@ -711,21 +819,32 @@ void Solver::refine(int k, double*& V, std::vector<double>& D, int& m, double ep
   std::vector<double> Sh((size_t)ml * ml), w, Z, Ph((size_t)ml * ml);
   int it = 0;
   for (it = 1; it <= o_.max_refine; ++it) {
-    mqr(k, F, n, ml, "rq");
-    copy_block(F, ml, Q, ml, n, ml, s_);
-    applyM(k, Q, ml, W, ml, ml);
-    h2d(Dd, mu_prev.data(), ml);
-    scale_cols(Q, ml, Dd, F2, ml, n, ml, false, s_);
+    {
+      PhaseTimer pt(st_, 3, s_);
+      mqr(k, F, n, ml, "rq");
+      copy_block(F, ml, Q, ml, n, ml, s_);
+      applyM(k, Q, ml, W, ml, ml);
+      h2d(Dd, mu_prev.data(), ml);
+      scale_cols(Q, ml, Dd, F2, ml, n, ml, false, s_);
+    }
     std::vector<int> its;
-    pcg(k, W, ml, F2, ml, ml, eps_solve, true, st_ ? &its : nullptr);
+    {
+      PhaseTimer pt(st_, 0, s_);
+      pcg(k, W, ml, F2, ml, ml, eps_solve, true, st_ ? &its : nullptr);
+    }
     if (st_) {
       st_->pcg_A_calls[k] += ml;
       for (int x : its) st_->pcg_A_iters[k] += x;
     }
-    gram(W, ml, F2, ml, n, ml, ml, Sd, ml, work, s_);
-    d2h(Sh.data(), Sd, Sh.size());
-    sync();
-    dense::sym_eig(ml, Sh.data(), w, &Z);
+    {
+      PhaseTimer pt(st_, 3, s_);
+      gram(W, ml, F2, ml, n, ml, ml, Sd, ml, work, s_);
+      d2h(Sh.data(), Sd, Sh.size());
+    }
+    {
+      PhaseTimer pt(st_, 2, s_);
+      dense::sym_eig(ml, Sh.data(), w, &Z);
+    }
     for (int j = 0; j < ml; ++j) {
       Dn[j] = w[ml - 1 - j];
       for (int i = 0; i < ml; ++i) Ph[(size_t)i * ml + j] = Z[(size_t)i * ml + (ml - 1 - j)];
@@ -819,7 +938,8 @@ void Solver::final_pairs(double* V, const std::vector<double>& D, int m, int nev
   double* av = pool_.d("fp:av", nev);
   const int nb = col_dot(Vo, nev, Vo, nev, n, nev, pr, s_);
   reduce_partials(pr, nb, nev, cn, s_);
-  col_absmax(Vo, nev, n, nev, ai, av, s_);
+  const int* perm = h_.perm.empty() ? nullptr : h_.d_perm.p;
+  col_absmax(Vo, nev, n, nev, ai, av, perm, s_);
   std::vector<double> nrm(nev), amax(nev), scale(nev);
   d2h(nrm.data(), cn, nev);
   d2h(amax.data(), av, nev);
@@ -827,7 +947,7 @@ void Solver::final_pairs(double* V, const std::vector<double>& D, int m, int nev
   for (int j = 0; j < nev; ++j) scale[j] = (amax[j] < 0 ? -1.0 : 1.0) / std::sqrt(nrm[j]);
   double* sd = pool_.d("fp:sc", nev);
   h2d(sd, scale.data(), nev);
-  to_colmajor(Vo, nev, sd, evecs, n, nev, s_);
+  to_colmajor(Vo, nev, sd, evecs, n, nev, perm, s_);
   for (int j = 0; j < nev; ++j) evals[j] = lam[j];
   sync();
 }
@@ -852,6 +972,8 @@ void Solver::leftmost(int nev, double tol, double* evals, double* evecs) {
     std::memset(st_, 0, sizeof(eig_stats));
     st_->K = K;
   }
+  ev_pending_.clear();
+  ev_bytes_.clear();
   double* V = pool_.d("VA", 1);
   std::vector<double> D;
   int m = 0;
@@ -895,8 +1017,11 @@ void Solver::leftmost(int nev, double tol, double* evals, double* evecs) {
     if (st_) st_->seconds_level[k] = std::chrono::duration<double>(std::chrono::steady_clock::now() - tl).count();
   }
   if (K == 0) extend(0, V, D, m, nev, tol, 0.0, dd[0], true);
-  multiplicity_check(V, D, m, tol, dd[0]);
-  final_pairs(V, D, m, nev, tol, evals, evecs);
+  {
+    PhaseTimer pt(st_, 7, s_);
+    multiplicity_check(V, D, m, tol, dd[0]);
+    final_pairs(V, D, m, nev, tol, evals, evecs);
+  }
   if (st_) {
     st_->nconv = nev;
     st_->seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -904,9 +1029,23 @@ void Solver::leftmost(int nev, double tol, double* evals, double* evecs) {
 }
 
 // ------------------------------------------------------------------ exposed blocks
-void Solver::apply_op(int level, int op, const double* X, double* Y, int b) {
+void Solver::apply_op(int level, int op, const double* Xu, double* Yu, int b) {
   MMD_REQUIRE(level >= 0 && level <= h_.K, MMD_EINVAL, "level out of range");
   MMD_REQUIRE(b > 0, MMD_EINVAL, "b must be positive");
+  MMD_REQUIRE(op >= 0 && op <= 5, MMD_EINVAL, "unknown operator");
+  // level-0 vectors are in the caller's numbering at the boundary
+  const bool perm = level == 0 && !h_.perm.empty();
+  const int n0 = nlev(0);
+  const bool in0 = perm && (op == 0 || op == 1 || op == 4);
+  const bool out0 = perm && (op == 0 || op == 1 || op == 3 || op == 5);
+  const double* X = Xu;
+  double* Y = Yu;
+  if (in0) {
+    double* t = pool_.d("ap:in", (size_t)n0 * b);
+    permute_rows(Xu, b, t, b, n0, b, h_.d_perm.p, false, s_);
+    X = t;
+  }
+  if (out0) Y = pool_.d("ap:out", (size_t)n0 * b);
   switch (op) {
     case 0: applyA(level, X, b, Y, b, b); break;
     case 1: applyM(level, X, b, Y, b, b); break;
@@ -928,6 +1067,7 @@ void Solver::apply_op(int level, int op, const double* X, double* Y, int b) {
       break;
     default: throw Error(MMD_EINVAL, "unknown operator");
   }
+  if (out0) permute_rows(Y, b, Yu, b, n0, b, h_.d_perm.p, true, s_);
 }
 
 void Solver::solve(int level, int kind, const double* rhs, double* X, int b, bool use_x0,
@@ -937,7 +1077,17 @@ void Solver::solve(int level, int kind, const double* rhs, double* X, int b, boo
   MMD_REQUIRE(tol > 0 && tol < 1, MMD_EINVAL, "tol must be in (0, 1)");
   std::vector<int> it;
   if (kind == 0) {
-    pcg(level, rhs, b, X, b, b, tol, use_x0, &it);
+    if (level == 0 && !h_.perm.empty()) {
+      const int n0 = nlev(0);
+      double* r = pool_.d("sv:rhs", (size_t)n0 * b);
+      double* x = pool_.d("sv:x", (size_t)n0 * b);
+      permute_rows(rhs, b, r, b, n0, b, h_.d_perm.p, false, s_);
+      if (use_x0) permute_rows(X, b, x, b, n0, b, h_.d_perm.p, false, s_);
+      pcg(level, r, b, x, b, b, tol, use_x0, &it);
+      permute_rows(x, b, X, b, n0, b, h_.d_perm.p, true, s_);
+    } else {
+      pcg(level, rhs, b, X, b, b, tol, use_x0, &it);
+    }
   } else if (kind == 1) {
     MMD_REQUIRE(level < h_.K, MMD_EINVAL, "B needs a coarser level");
     const int nred = h_.dev[level + 1].H.nred;

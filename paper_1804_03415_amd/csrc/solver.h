@@ -27,6 +27,7 @@ struct SolveResult {
 class Solver {
  public:
   Solver(mmd_handle& h, hipStream_t s, const eig_opts& o, eig_stats* st);
+  ~Solver();
 
   // eig_leftmost: evals ascending (host), evecs column-major n x nev (device)
   void leftmost(int nev, double tol, double* evals, double* evecs);
@@ -76,7 +77,18 @@ class Solver {
   void final_pairs(double* V, const std::vector<double>& D, int m, int nev, double tol,
                    double* evals, double* evecs);
 
-  void sync() { MMD_HIP(hipStreamSynchronize(s_)); }
+  void sync() {
+    MMD_HIP(hipStreamSynchronize(s_));
+    harvest_timers();
+  }
+  // HIP-event timing of the level-0 block SpMM (only when stats are requested)
+  void spmm0_begin();
+  void spmm0_end(double bytes, int b);
+  void harvest_timers();
+  std::vector<hipEvent_t> ev_free_;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending_;
+  std::vector<double> ev_bytes_;
+  hipEvent_t ev_open_ = nullptr;
   template <typename T>
   void d2h(T* dst, const T* src, size_t n) {
     MMD_HIP(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToHost, s_));
