@@ -235,3 +235,18 @@ def by_name(name: str) -> Problem:
         "knn_200000": lambda: knn_gmm(200000, 10, 1),
     }
     return table[name]()
+
+
+def rgg_window(p: Problem, frac: float, shift: float = 1e-6) -> Problem:
+    """The RGG of the points of p inside the corner square of area `frac`.
+
+    Same point density, radius and weights as p; the Laplacian is rebuilt from
+    the kept edges (a spatial sample of the same workload).
+    """
+    w = float(np.sqrt(frac))
+    keep = np.where((p.coords[:, 0] < w) & (p.coords[:, 1] < w))[0]
+    A = p.scipy()[keep][:, keep].tocoo()
+    off = A.row < A.col
+    rowptr, col, val = laplacian_from_edges(keep.size, A.row[off], A.col[off], -A.data[off], shift)
+    return Problem(f"{p.name}_window{frac:g}", keep.size, rowptr, col, val, p.coords[keep].copy(),
+                   None, {"parent": p.name, "frac": frac, "shift": shift})
