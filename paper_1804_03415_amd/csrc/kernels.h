@@ -115,6 +115,12 @@ void scale_vec_dev(const double* x, const double* scal, bool inv_sqrt, double* y
 // Y(:, idx[j]) gathered into Z(:, j)
 void gather_cols(const double* Y, int ldy, const int* idx, double* Z, int ldz, int n, int b,
                  hipStream_t s);
+// Y(:, j) scattered into Z(:, idx[j])
+void scatter_cols(const double* Y, int ldy, const int* idx, double* Z, int ldz, int n, int b,
+                  hipStream_t s);
+// per-column CG scalars of columns idx[0..m) of src into columns 0..m of dst
+// (notspd is not copied)
+void gather_scalars(ColScalars src, ColScalars dst, const int* idx, int m, hipStream_t s);
 // column-major output: out[c*n + perm[i]] = X[i*ldx + c] * colscale[c] (perm may be null)
 void to_colmajor(const double* X, int ldx, const double* colscale, double* out, int n, int b,
                  const int* perm, hipStream_t s);

@@ -41,8 +41,8 @@ inline void check_launch() {
 // One wavefront handles R = 64 / (LPR * CT) rows and a tile of CT columns;
 // lane = (r, s, c): c = lane % CT, s = (lane / CT) % LPR, r = lane / (CT*LPR).
 // The LPR lanes of a (row, column) pair stride over the row's nonzeros and are
-// combined with xor shuffles.  Rows are visited in a grid-stride loop so each
-// block can keep per-column partial dot products for the fused CG epilogue.
+// combined with xor shuffles.  A block walks a contiguous run of row groups so
+// it can keep per-column partial dot products for the fused CG epilogue.
 template <int LPR, int CT, bool EDGE, bool FUSE, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_spmm(
     int n_rows, const int* __restrict__ rowptr, const int* __restrict__ col,
@@ -65,7 +65,11 @@ __global__ __launch_bounds__(kBlock) void k_spmm(
   double dsum = 0.0;
   const int groups = (n_rows + R - 1) / R;
   const int bx = xcd_block(blockIdx.x, gridDim.x);
-  for (int g = bx * WPB + wid; g < groups; g += gridDim.x * WPB) {
+  // each block owns a contiguous run of row groups, so the blocks of one XCD
+  // (consecutive after xcd_block) sweep one contiguous band of rows
+  const int per = ((groups + (int)gridDim.x - 1) / (int)gridDim.x + WPB - 1) / WPB * WPB;
+  const int g_hi = min(groups, (bx + 1) * per);
+  for (int g = bx * per + wid; g < g_hi; g += WPB) {
     const int row = g * R + r;
     double acc = 0.0;
     double xi = 0.0;
@@ -276,29 +280,67 @@ __global__ __launch_bounds__(1024) void k_coldot(const double* __restrict__ X, i
   }
 }
 
-__global__ void k_reduce_partials(const double* __restrict__ partial, int nblk, int b,
-                                  double* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= b) return;
+// Per-column sums of a partial-sum array partial[q * b + c], q < nblk.  A block
+// of kScThreads threads serves kScCols consecutive columns: lane t reads column
+// t % kScCols of slices q = t / kScCols, t / kScCols + kScSlices, ... (one
+// 128-byte line per slice row), the slice sums are combined in LDS in a fixed
+// order, and the result is valid in threads t < kScCols.
+constexpr int kScCols = 16;
+constexpr int kScThreads = 1024;
+constexpr int kScSlices = kScThreads / kScCols;
+
+__device__ inline double col_sum(const double* __restrict__ p, int nblk, int b, bool want) {
+  __shared__ double sh[kScThreads];
+  const int c = blockIdx.x * kScCols + threadIdx.x % kScCols;
+  const int sl = threadIdx.x / kScCols;
   double t = 0.0;
-  for (int q = 0; q < nblk; ++q) t += partial[(size_t)q * b + c];
-  out[c] = t;
+  if (want && c < b) {
+    double t1 = 0.0;
+    int q = sl;
+    for (; q + kScSlices < nblk; q += 2 * kScSlices) {
+      t += p[(size_t)q * b + c];
+      t1 += p[(size_t)(q + kScSlices) * b + c];
+    }
+    if (q < nblk) t += p[(size_t)q * b + c];
+    t += t1;
+  }
+  sh[threadIdx.x] = t;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x < kScCols)
+    for (int q = 0; q < kScSlices; ++q) r += sh[q * kScCols + threadIdx.x];
+  __syncthreads();
+  return r;
 }
 
-__device__ inline double sum_part(const double* __restrict__ p, int nblk, int b, int c) {
-  double t = 0.0;
-  for (int q = 0; q < nblk; ++q) t += p[(size_t)q * b + c];
-  return t;
+inline int sc_grid(int b) { return ceil_div(b, kScCols); }
+
+__device__ inline int sc_col() { return blockIdx.x * kScCols + threadIdx.x; }
+
+__global__ __launch_bounds__(kScThreads) void k_reduce_partials(
+    const double* __restrict__ partial, int nblk, int b, double* __restrict__ out) {
+  const double v = col_sum(partial, nblk, b, true);
+  const int c = sc_col();
+  if (threadIdx.x < kScCols && c < b) out[c] = v;
+}
+
+// The activity flag of column c as seen by all lanes of the block (inactive
+// columns skip their reads).
+__device__ inline bool col_active(const ColScalars& sc, int b) {
+  const int c = blockIdx.x * kScCols + threadIdx.x % kScCols;
+  return c < b && sc.active[c] != 0;
 }
 
 // ------------------------------------------------------------------ CG scalars
-__global__ void k_cg_init(ColScalars sc, const double* __restrict__ pbn,
-                          const double* __restrict__ prr, int nblk, int b, double tol,
-                          const int* __restrict__ parent) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= b) return;
-  const double bn2 = sum_part(pbn, nblk, b, c);
-  const double rr = prr ? sum_part(prr, nblk, b, c) : bn2;
+__global__ __launch_bounds__(kScThreads) void k_cg_init(ColScalars sc,
+                                                        const double* __restrict__ pbn,
+                                                        const double* __restrict__ prr,
+                                                        int nblk, int b, double tol,
+                                                        const int* __restrict__ parent) {
+  const double bn2 = col_sum(pbn, nblk, b, true);
+  const double rr = prr ? col_sum(prr, nblk, b, true) : bn2;
+  const int c = sc_col();
+  if (threadIdx.x >= kScCols || c >= b) return;
   sc.bn2[c] = bn2;
   sc.rr2[c] = rr;
   sc.rr[c] = rr;
@@ -310,14 +352,17 @@ __global__ void k_cg_init(ColScalars sc, const double* __restrict__ pbn,
   sc.active[c] = (par && bn2 > 0.0 && rr > tol * tol * bn2) ? 1 : 0;
 }
 
-__global__ void k_cg_alpha(ColScalars sc, const double* __restrict__ ppq, int nblk, int b) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= b) return;
-  if (!sc.active[c]) {
+__global__ __launch_bounds__(kScThreads) void k_cg_alpha(ColScalars sc,
+                                                         const double* __restrict__ ppq,
+                                                         int nblk, int b) {
+  const bool act = col_active(sc, b);
+  const double pq = col_sum(ppq, nblk, b, act);
+  const int c = sc_col();
+  if (threadIdx.x >= kScCols || c >= b) return;
+  if (!act) {
     sc.alpha[c] = 0.0;
     return;
   }
-  const double pq = sum_part(ppq, nblk, b, c);
   if (!(pq > 0.0)) {
     sc.notspd[0] = 1;
     sc.active[c] = 0;
@@ -327,14 +372,17 @@ __global__ void k_cg_alpha(ColScalars sc, const double* __restrict__ ppq, int nb
   sc.alpha[c] = sc.rr[c] / pq;
 }
 
-__global__ void k_cg_beta(ColScalars sc, const double* __restrict__ prr, int nblk, int b) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= b) return;
-  if (!sc.active[c]) {
+__global__ __launch_bounds__(kScThreads) void k_cg_beta(ColScalars sc,
+                                                        const double* __restrict__ prr,
+                                                        int nblk, int b) {
+  const bool act = col_active(sc, b);
+  const double rn = col_sum(prr, nblk, b, act);
+  const int c = sc_col();
+  if (threadIdx.x >= kScCols || c >= b) return;
+  if (!act) {
     sc.beta[c] = 0.0;
     return;
   }
-  const double rn = sum_part(prr, nblk, b, c);
   sc.iters[c] += 1;
   sc.rr2[c] = rn;
   if (rn <= sc.tol2[c] * sc.bn2[c]) {
@@ -346,11 +394,13 @@ __global__ void k_cg_beta(ColScalars sc, const double* __restrict__ prr, int nbl
   sc.rr[c] = rn;
 }
 
-__global__ void k_pcg_conv(ColScalars sc, const double* __restrict__ prr, int nblk, int b) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= b) return;
-  if (!sc.active[c]) return;
-  const double rn = sum_part(prr, nblk, b, c);
+__global__ __launch_bounds__(kScThreads) void k_pcg_conv(ColScalars sc,
+                                                         const double* __restrict__ prr,
+                                                         int nblk, int b) {
+  const bool act = col_active(sc, b);
+  const double rn = col_sum(prr, nblk, b, act);
+  const int c = sc_col();
+  if (threadIdx.x >= kScCols || c >= b || !act) return;
   sc.iters[c] += 1;
   sc.rr2[c] = rn;
   if (rn <= sc.tol2[c] * sc.bn2[c]) {
@@ -359,16 +409,19 @@ __global__ void k_pcg_conv(ColScalars sc, const double* __restrict__ prr, int nb
   }
 }
 
-__global__ void k_pcg_beta(ColScalars sc, const double* __restrict__ prz,
-                           const double* __restrict__ przo, int nblk, int b) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= b) return;
-  if (!sc.active[c]) {
+__global__ __launch_bounds__(kScThreads) void k_pcg_beta(ColScalars sc,
+                                                         const double* __restrict__ prz,
+                                                         const double* __restrict__ przo,
+                                                         int nblk, int b) {
+  const bool act = col_active(sc, b);
+  const double rz = col_sum(prz, nblk, b, act);
+  const double rzo = col_sum(przo, nblk, b, act);
+  const int c = sc_col();
+  if (threadIdx.x >= kScCols || c >= b) return;
+  if (!act) {
     sc.beta[c] = 0.0;
     return;
   }
-  const double rz = sum_part(prz, nblk, b, c);
-  const double rzo = sum_part(przo, nblk, b, c);
   sc.beta[c] = (rz - rzo) / sc.rr[c];
   sc.rr[c] = rz;
 }
@@ -469,6 +522,28 @@ __global__ void k_gather_cols(const double* __restrict__ Y, int ldy, const int* 
   if (t >= (int64_t)n * b) return;
   const int64_t i = t / b, c = t % b;
   Z[i * ldz + c] = Y[i * ldy + idx[c]];
+}
+
+__global__ void k_scatter_cols(const double* __restrict__ Y, int ldy, const int* __restrict__ idx,
+                               double* __restrict__ Z, int ldz, int n, int b) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * b) return;
+  const int64_t i = t / b, c = t % b;
+  Z[i * ldz + idx[c]] = Y[i * ldy + c];
+}
+
+__global__ void k_gather_scalars(ColScalars a, ColScalars d, const int* __restrict__ idx, int m) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  const int c = idx[j];
+  d.rr[j] = a.rr[c];
+  d.rr2[j] = a.rr2[c];
+  d.alpha[j] = a.alpha[c];
+  d.beta[j] = a.beta[c];
+  d.bn2[j] = a.bn2[c];
+  d.tol2[j] = a.tol2[c];
+  d.active[j] = a.active[c];
+  d.iters[j] = a.iters[c];
 }
 
 __global__ void k_to_colmajor(const double* __restrict__ X, int ldx,
@@ -734,39 +809,39 @@ int col_dot2(const double* X, int ldx, const double* Y1, const double* Y2, int l
 }
 
 void reduce_partials(const double* partial, int nblk, int b, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_partials, dim3(ceil_div(b, kBlock)), dim3(kBlock), 0, s, partial,
+  hipLaunchKernelGGL(k_reduce_partials, dim3(sc_grid(b)), dim3(kScThreads), 0, s, partial,
                      nblk, b, out);
   check_launch();
 }
 
 void cg_init(ColScalars sc, const double* part_bn, const double* part_rr, int nblk, int b,
              double tol, const int* parent_active, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_init, dim3(ceil_div(b, kBlock)), dim3(kBlock), 0, s, sc, part_bn,
+  hipLaunchKernelGGL(k_cg_init, dim3(sc_grid(b)), dim3(kScThreads), 0, s, sc, part_bn,
                      part_rr, nblk, b, tol, parent_active);
   check_launch();
 }
 
 void cg_alpha(ColScalars sc, const double* part_pq, int nblk, int b, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_alpha, dim3(ceil_div(b, kBlock)), dim3(kBlock), 0, s, sc, part_pq,
+  hipLaunchKernelGGL(k_cg_alpha, dim3(sc_grid(b)), dim3(kScThreads), 0, s, sc, part_pq,
                      nblk, b);
   check_launch();
 }
 
 void cg_beta(ColScalars sc, const double* part_rr, int nblk, int b, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_beta, dim3(ceil_div(b, kBlock)), dim3(kBlock), 0, s, sc, part_rr,
+  hipLaunchKernelGGL(k_cg_beta, dim3(sc_grid(b)), dim3(kScThreads), 0, s, sc, part_rr,
                      nblk, b);
   check_launch();
 }
 
 void pcg_conv(ColScalars sc, const double* part_rr, int nblk, int b, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_conv, dim3(ceil_div(b, kBlock)), dim3(kBlock), 0, s, sc, part_rr,
+  hipLaunchKernelGGL(k_pcg_conv, dim3(sc_grid(b)), dim3(kScThreads), 0, s, sc, part_rr,
                      nblk, b);
   check_launch();
 }
 
 void pcg_beta(ColScalars sc, const double* part_rz, const double* part_rzo, int nblk, int b,
               hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_beta, dim3(ceil_div(b, kBlock)), dim3(kBlock), 0, s, sc, part_rz,
+  hipLaunchKernelGGL(k_pcg_beta, dim3(sc_grid(b)), dim3(kScThreads), 0, s, sc, part_rz,
                      part_rzo, nblk, b);
   check_launch();
 }
@@ -837,6 +912,21 @@ void gather_cols(const double* Y, int ldy, const int* idx, double* Z, int ldz, i
   if ((int64_t)n * b == 0) return;
   hipLaunchKernelGGL(k_gather_cols, dim3(ew_grid((int64_t)n * b)), dim3(kBlock), 0, s, Y, ldy,
                      idx, Z, ldz, n, b);
+  check_launch();
+}
+
+void scatter_cols(const double* Y, int ldy, const int* idx, double* Z, int ldz, int n, int b,
+                  hipStream_t s) {
+  if ((int64_t)n * b == 0) return;
+  hipLaunchKernelGGL(k_scatter_cols, dim3(ew_grid((int64_t)n * b)), dim3(kBlock), 0, s, Y, ldy,
+                     idx, Z, ldz, n, b);
+  check_launch();
+}
+
+void gather_scalars(ColScalars src, ColScalars dst, const int* idx, int m, hipStream_t s) {
+  if (m == 0) return;
+  hipLaunchKernelGGL(k_gather_scalars, dim3(ceil_div(m, kBlock)), dim3(kBlock), 0, s, src, dst,
+                     idx, m);
   check_launch();
 }
 

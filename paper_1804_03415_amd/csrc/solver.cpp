@@ -240,10 +240,18 @@ void Solver::cg(int k, OpKind op, const double* B, int ldb, double* X, int ldx, 
   const CsrView* csr = nullptr;
   if (op == OpKind::A) csr = &h_.dev[k].A;
   if (op == OpKind::M) csr = &h_.dev[k].M;
+  // working set: bc columns (the unconverged ones once compacted); column j of
+  // the working set is caller column cols[j], its iterate lives in Xw (ld ldw)
+  int bc = b;
+  double* Xw = X;
+  int ldw = ldx;
+  std::vector<int> cols(b);
+  for (int c = 0; c < b; ++c) cols[c] = c;
+  std::vector<int> it_host(b, 0);
   auto apply = [&](const double* x, int lx, double* y, int ly) {
-    if (op == OpKind::A) applyA(k, x, lx, y, ly, b);
-    else if (op == OpKind::M) applyM(k, x, lx, y, ly, b);
-    else applyB(k, x, lx, y, ly, b);
+    if (op == OpKind::A) applyA(k, x, lx, y, ly, bc);
+    else if (op == OpKind::M) applyM(k, x, lx, y, ly, bc);
+    else applyB(k, x, lx, y, ly, bc);
   };
   if (use_x0) {
     apply(X, ldx, R, b);
@@ -258,35 +266,49 @@ void Solver::cg(int k, OpKind op, const double* B, int ldb, double* X, int ldx, 
   MMD_HIP(hipMemsetAsync(sc.notspd, 0, sizeof(int), s_));
   auto iterate = [&](bool first) {
     int np;
-    if (csr && b <= 32) {
-      np = spmm(*csr, R, b, Q, b, b, s_, true, first, sc.beta, P, b, p1);
-    } else if (csr) {
-      // wide blocks: direction update over the full grid, p.q as a separate reduction
-      const bool timed = k == 0 && op == OpKind::A;
+    if (csr) {
+      // fused: P = R + beta P, Q = A R + beta Q (= A P), partial p.q per block
+      const bool timed = k == 0 && op == OpKind::A && bc > 32;
       if (timed) spmm0_begin();
-      spmm(*csr, R, b, Q, b, b, s_, true, first, sc.beta, P, b, nullptr);
+      np = spmm(*csr, R, bc, Q, bc, bc, s_, true, first, sc.beta, P, bc, p1);
       if (timed) {
         // matrix once (weights + columns, row pointers, self-loops), R read once,
         // P and Q read and written once
         const double nnz = static_cast<double>(csr->nnz);
-        const double bytes = 12.0 * nnz + 12.0 * n + 40.0 * n * static_cast<double>(b) +
-                             (first ? -16.0 * n * static_cast<double>(b) : 0.0);
-        spmm0_end(bytes, b);
+        const double bytes = 12.0 * nnz + 12.0 * n + 40.0 * n * static_cast<double>(bc) +
+                             (first ? -16.0 * n * static_cast<double>(bc) : 0.0);
+        spmm0_end(bytes, bc);
       }
-      np = col_dot(P, b, Q, b, n, b, p1, s_);
     } else {
-      xpay(R, b, P, b, n, b, sc.beta, first, s_);
-      apply(P, b, Q, b);
-      np = col_dot(P, b, Q, b, n, b, p1, s_);
+      xpay(R, bc, P, bc, n, bc, sc.beta, first, s_);
+      apply(P, bc, Q, bc);
+      np = col_dot(P, bc, Q, bc, n, bc, p1, s_);
     }
-    cg_alpha(sc, p1, np, b, s_);
-    const int nu = cg_update(X, ldx, R, P, Q, b, n, b, sc.alpha, p2, s_);
-    cg_beta(sc, p2, nu, b, s_);
+    cg_alpha(sc, p1, np, bc, s_);
+    const int nu = cg_update(Xw, ldw, R, P, Q, bc, n, bc, sc.alpha, p2, s_);
+    cg_beta(sc, p2, nu, bc, s_);
   };
   if (fixed_iters > 0) {
     for (int t = 0; t < fixed_iters; ++t) iterate(t == 0);
     return;
   }
+  // the working state moves to a compact copy once a quarter of its columns
+  // have converged; converged columns keep their final iterate in X
+  int* d_idx = pool_.i(tag + ":cidx", b);
+  int* d_cols = pool_.i(tag + ":ccol", b);
+  int stage = 0;
+  auto flush_x = [&]() {  // working iterates back to the caller's columns
+    if (Xw == X) return;
+    h2d(d_cols, cols.data(), bc);
+    scatter_cols(Xw, ldw, d_cols, X, ldx, n, bc, s_);
+    sync();  // the host index list must outlive the copy
+  };
+  auto take_iters = [&]() {
+    hi_.ensure(bc);
+    d2h(hi_.p, sc.iters, bc);
+    sync();
+    for (int c = 0; c < bc; ++c) it_host[cols[c]] = hi_.p[c];
+  };
   const int maxit = 100000;
   int done = 0, chunk = 4;
   bool first = true;
@@ -296,23 +318,51 @@ void Solver::cg(int k, OpKind op, const double* B, int ldb, double* X, int ldx, 
       first = false;
     }
     done += chunk;
-    hi_.ensure(b + 1);
-    d2h(hi_.p, sc.active, b);
-    d2h(hi_.p + b, sc.notspd, 1);
+    hi_.ensure(bc + 1);
+    d2h(hi_.p, sc.active, bc);
+    d2h(hi_.p + bc, sc.notspd, 1);
     sync();
-    MMD_REQUIRE(hi_.p[b] == 0, MMD_ENOTSPD, "CG curvature p^T A p <= 0");
-    bool any = false;
-    for (int c = 0; c < b; ++c) any |= hi_.p[c] != 0;
-    if (!any) break;
+    MMD_REQUIRE(hi_.p[bc] == 0, MMD_ENOTSPD, "CG curvature p^T A p <= 0");
+    std::vector<int> keep;
+    for (int c = 0; c < bc; ++c)
+      if (hi_.p[c] != 0) keep.push_back(c);
+    if (keep.empty()) break;
     MMD_REQUIRE(done < maxit, MMD_ENOCONV, "CG reached the iteration cap");
     chunk = std::min(chunk * 2, 64);
+    const int na = static_cast<int>(keep.size());
+    if (bc >= 16 && 4 * na <= 3 * bc) {
+      take_iters();
+      flush_x();
+      ++stage;
+      const std::string st = tag + ":c" + std::to_string(stage & 1);
+      double* R2 = pool_.d(st + "R", (size_t)n * na);
+      double* P2 = pool_.d(st + "P", (size_t)n * na);
+      double* Q2 = pool_.d(st + "Q", (size_t)n * na);
+      double* X2 = pool_.d(st + "X", (size_t)n * na);
+      ColScalars sc2 = make_scalars(pool_, st, b);
+      sc2.notspd = sc.notspd;
+      h2d(d_idx, keep.data(), na);
+      gather_cols(R, bc, d_idx, R2, na, n, na, s_);
+      gather_cols(P, bc, d_idx, P2, na, n, na, s_);
+      gather_cols(Q, bc, d_idx, Q2, na, n, na, s_);
+      gather_cols(Xw, ldw, d_idx, X2, na, n, na, s_);
+      gather_scalars(sc, sc2, d_idx, na, s_);
+      sync();  // keep (host) must outlive its copy
+      std::vector<int> cols2(na);
+      for (int j = 0; j < na; ++j) cols2[j] = cols[keep[j]];
+      cols.swap(cols2);
+      R = R2;
+      P = P2;
+      Q = Q2;
+      Xw = X2;
+      ldw = na;
+      sc = sc2;
+      bc = na;
+    }
   }
-  if (iters) {
-    iters->resize(b);
-    d2h(hi_.p, sc.iters, b);
-    sync();
-    std::copy(hi_.p, hi_.p + b, iters->begin());
-  }
+  take_iters();
+  flush_x();
+  if (iters) *iters = it_host;
 }
 
 bool Solver::pcg_single(int k, const double* B, double* X, double tol, bool use_x0,
