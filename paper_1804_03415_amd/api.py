@@ -62,6 +62,7 @@ class Decomposition:
         h = ctypes.c_void_p()
         check(lib().mmd_build(ctypes.byref(c), ctypes.byref(o), _lib._stream(stream), ctypes.byref(h)))
         self.h = h
+        self._L = lib()
         self.n = n
 
     @classmethod
@@ -69,9 +70,12 @@ class Decomposition:
         return cls(p.rowptr, p.col, p.val, coords=None if p.grid else p.coords, grid=p.grid, **opts)
 
     def __del__(self):
+        # the library object is held by the instance, so freeing works also
+        # while the interpreter tears module globals down
         h = getattr(self, "h", None)
-        if h is not None and h.value:
-            lib().mmd_free(h)
+        L = getattr(self, "_L", None)
+        if h is not None and h.value and L is not None:
+            L.mmd_free(h)
             self.h = None
 
     def info(self):

@@ -34,7 +34,7 @@ struct HouseView {
 };
 
 // Work buffers for column reductions.
-constexpr int kRedBlocks = 512;  // max blocks of a reduction grid
+constexpr int kRedBlocks = 1024;  // max blocks of a reduction grid
 
 // ---------------------------------------------------------------- SpMM
 // Y = A X.  fuse != 0 selects the CG form:

@@ -24,14 +24,6 @@ constexpr int kBlock = 256;
 
 inline int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
 
-// Workgroups are dealt to the 8 XCDs round-robin; renumber them so the blocks
-// of one XCD cover a contiguous range of rows and share that XCD's L2.
-__device__ inline int xcd_block(int bx, int gx) {
-  constexpr int kXcd = 8;
-  if (gx % kXcd) return bx;
-  return (bx % kXcd) * (gx / kXcd) + bx / kXcd;
-}
-
 inline void check_launch() {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) throw Error(MMD_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -41,8 +33,8 @@ inline void check_launch() {
 // One wavefront handles R = 64 / (LPR * CT) rows and a tile of CT columns;
 // lane = (r, s, c): c = lane % CT, s = (lane / CT) % LPR, r = lane / (CT*LPR).
 // The LPR lanes of a (row, column) pair stride over the row's nonzeros and are
-// combined with xor shuffles.  A block walks a contiguous run of row groups so
-// it can keep per-column partial dot products for the fused CG epilogue.
+// combined with xor shuffles.  A block walks several row groups so it can keep
+// per-column partial dot products for the fused CG epilogue.
 template <int LPR, int CT, bool EDGE, bool FUSE, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_spmm(
     int n_rows, const int* __restrict__ rowptr, const int* __restrict__ col,
@@ -64,12 +56,15 @@ __global__ __launch_bounds__(kBlock) void k_spmm(
   const double bt = (FUSE && cok && !first) ? beta[colx] : 0.0;
   double dsum = 0.0;
   const int groups = (n_rows + R - 1) / R;
-  const int bx = xcd_block(blockIdx.x, gridDim.x);
-  // each block owns a contiguous run of row groups, so the blocks of one XCD
-  // (consecutive after xcd_block) sweep one contiguous band of rows
-  const int per = ((groups + (int)gridDim.x - 1) / (int)gridDim.x + WPB - 1) / WPB * WPB;
-  const int g_hi = min(groups, (bx + 1) * per);
-  for (int g = bx * per + wid; g < g_hi; g += WPB) {
+  // each XCD (workgroups are dealt to the 8 XCDs round-robin) sweeps its own
+  // contiguous eighth of the row groups, its resident blocks moving through it
+  // as one band
+  const int nx = (gridDim.x % 8 == 0) ? 8 : 1;
+  const int bpx = gridDim.x / nx;
+  const int xcd = blockIdx.x % nx, bl = blockIdx.x / nx;
+  const int gpx = (groups + nx - 1) / nx;
+  const int g_hi = min(groups, (xcd + 1) * gpx);
+  for (int g = xcd * gpx + bl * WPB + wid; g < g_hi; g += bpx * WPB) {
     const int row = g * R + r;
     double acc = 0.0;
     double xi = 0.0;
@@ -131,6 +126,145 @@ __global__ __launch_bounds__(kBlock) void k_spmm(
   }
 }
 
+// Blocks of more than 32 columns: one wavefront per (row, 64-column tile),
+// two rows per wavefront in flight.  The lanes first load up to 64 of the
+// row's column indices and weights with one vector load, then broadcast them
+// with readlane, so every gather of the row is issued back to back instead of
+// waiting on its index load.  Slots past the end of a row's nonzeros gather
+// row 0 with weight 0.  Each XCD (workgroups are dealt round-robin to the
+// 8 XCDs) sweeps its own contiguous eighth of the rows.  Fused CG epilogue as
+// in k_spmm.
+constexpr int kStep = 8;
+
+__device__ inline double readlane_d(double v, int k) {
+  const long long u = __double_as_longlong(v);
+  const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(u), k));
+  const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(u >> 32), k));
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+template <bool EDGE, bool FUSE>
+__global__ __launch_bounds__(kBlock) void k_spmm_r64(
+    int n_rows, const int* __restrict__ rowptr, const int* __restrict__ col,
+    const double* __restrict__ val, const double* __restrict__ diag,
+    const double* __restrict__ X, int ldx, double* __restrict__ Y, int ldy, int b, int first,
+    const double* __restrict__ beta, double* __restrict__ P, int ldp,
+    double* __restrict__ partial) {
+  constexpr int WPB = kBlock / kWave;
+  __shared__ double red[WPB * kWave];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int cc = blockIdx.y * kWave + lane;
+  const bool cok = cc < b;
+  const int cx = cok ? cc : 0;  // lanes past b read column 0 and store nothing
+  const double bt = (FUSE && cok && !first) ? beta[cc] : 0.0;
+  double dsum = 0.0;
+  const int nx = (gridDim.x % 8 == 0) ? 8 : 1;
+  const int bpx = gridDim.x / nx;
+  const int xcd = blockIdx.x % nx, bl = blockIdx.x / nx;
+  const int rpx = (n_rows + nx - 1) / nx;
+  const int rhi = min(n_rows, (xcd + 1) * rpx);
+  const int stride = bpx * WPB;
+  for (int row0 = xcd * rpx + bl * WPB + wid; row0 < rhi; row0 += 2 * stride) {
+    const int row1 = row0 + stride;
+    const bool ok1 = row1 < rhi;
+    const int r1 = ok1 ? row1 : row0;
+    const int lo0 = rowptr[row0], hi0 = rowptr[row0 + 1];
+    const int lo1 = ok1 ? rowptr[row1] : 0, hi1 = ok1 ? rowptr[row1 + 1] : 0;
+    const double xi0 = EDGE ? X[(size_t)row0 * ldx + cx] : 0.0;
+    const double xi1 = EDGE ? X[(size_t)r1 * ldx + cx] : 0.0;
+    double a0 = 0.0, a1 = 0.0;
+    for (int b0 = lo0, b1 = lo1; b0 < hi0 || b1 < hi1; b0 += kWave, b1 += kWave) {
+      const int n0 = max(0, min(kWave, hi0 - b0)), n1 = max(0, min(kWave, hi1 - b1));
+      const int jv0 = lane < n0 ? col[b0 + lane] : 0;
+      const double vv0 = lane < n0 ? val[b0 + lane] : 0.0;
+      const int jv1 = lane < n1 ? col[b1 + lane] : 0;
+      const double vv1 = lane < n1 ? val[b1 + lane] : 0.0;
+      // steps of kStep slots with a fixed trip count, so all 2 * kStep gathers
+      // of a step are in flight together (padding slots carry weight 0)
+      const int m = max(n0, n1);
+      for (int k0 = 0; k0 < m; k0 += kStep) {
+        double x0[kStep], x1[kStep], w0[kStep], w1[kStep];
+#pragma unroll
+        for (int q = 0; q < kStep; ++q) {
+          const int j0 = __builtin_amdgcn_readlane(jv0, k0 + q);
+          const int j1 = __builtin_amdgcn_readlane(jv1, k0 + q);
+          w0[q] = readlane_d(vv0, k0 + q);
+          w1[q] = readlane_d(vv1, k0 + q);
+          x0[q] = X[(size_t)j0 * ldx + cx];
+          x1[q] = X[(size_t)j1 * ldx + cx];
+        }
+#pragma unroll
+        for (int q = 0; q < kStep; ++q) {
+          if (EDGE) {
+            a0 += w0[q] * (xi0 - x0[q]);
+            a1 += w1[q] * (xi1 - x1[q]);
+          } else {
+            a0 += w0[q] * x0[q];
+            a1 += w1[q] * x1[q];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int row = u ? row1 : row0;
+      if ((u == 0 || ok1) && cok) {
+        const double xi = u ? xi1 : xi0;
+        double y = EDGE ? diag[row] * xi + (u ? a1 : a0) : (u ? a1 : a0);
+        const size_t iy = (size_t)row * ldy + cc;
+        if (FUSE) {
+          const size_t ip = (size_t)row * ldp + cc;
+          double pn;
+          if (first) {
+            pn = X[(size_t)row * ldx + cc];
+          } else {
+            y += bt * Y[iy];
+            pn = X[(size_t)row * ldx + cc] + bt * P[ip];
+          }
+          P[ip] = pn;
+          dsum += pn * y;
+        }
+        Y[iy] = y;
+      }
+    }
+  }
+  if (FUSE && partial != nullptr) {
+    red[wid * kWave + lane] = dsum;
+    __syncthreads();
+    if (threadIdx.x < kWave) {
+      double t = 0.0;
+      for (int w = 0; w < WPB; ++w) t += red[w * kWave + threadIdx.x];
+      const int c = blockIdx.y * kWave + threadIdx.x;
+      if (c < b) partial[(size_t)blockIdx.x * b + c] = t;
+    }
+  }
+}
+
+int launch_spmm_r64(const CsrView& A, const double* X, int ldx, double* Y, int ldy, int b,
+                    hipStream_t s, bool fuse, bool first, const double* beta, double* P,
+                    int ldp, double* partial) {
+  constexpr int WPB = kBlock / kWave;
+  int gx = std::max(1, ceil_div(A.n_rows, 2 * WPB));
+  if (fuse && partial) gx = std::min(gx, kRedBlocks);
+  if (gx >= 8) gx = gx / 8 * 8;  // whole XCD rounds
+  dim3 grid(gx, ceil_div(b, kWave));
+  const bool edge = A.diag != nullptr;
+#define MMD_R64_CASE(E, F)                                                                  \
+  hipLaunchKernelGGL((k_spmm_r64<E, F>), grid, dim3(kBlock), 0, s, A.n_rows, A.rowptr, A.col, \
+                     A.val, A.diag, X, ldx, Y, ldy, b, first ? 1 : 0, beta, P, ldp, partial)
+  if (edge) {
+    if (fuse) MMD_R64_CASE(true, true);
+    else MMD_R64_CASE(true, false);
+  } else {
+    if (fuse) MMD_R64_CASE(false, true);
+    else MMD_R64_CASE(false, false);
+  }
+#undef MMD_R64_CASE
+  check_launch();
+  return gx;
+}
+
 template <int LPR, int CT>
 int launch_spmm_t(const CsrView& A, const double* X, int ldx, double* Y, int ldy, int b,
                   hipStream_t s, bool fuse, bool first, const double* beta, double* P, int ldp,
@@ -142,7 +276,7 @@ int launch_spmm_t(const CsrView& A, const double* X, int ldx, double* Y, int ldy
   const bool red = (fuse && partial != nullptr) || dotw != nullptr;
   if (red) gx = std::min(gx, kRedBlocks);
   gx = std::max(gx, 1);
-  if (gx >= 8) gx = (gx + 7) / 8 * 8;  // whole XCD rounds (see xcd_block)
+  if (gx >= 8) gx = (gx + 7) / 8 * 8;  // whole XCD rounds
   if (red) gx = std::min(gx, kRedBlocks);
   dim3 grid(gx, ceil_div(b, CT));
   const bool edge = A.diag != nullptr;
@@ -769,6 +903,7 @@ int spmm(const CsrView& A, const double* X, int ldx, double* Y, int ldy, int b, 
   }
   if (b <= 4) return launch_spmm_t<16, 4>(A, X, ldx, Y, ldy, b, s, fuse, first, beta, P, ldp, partial, dot_with, ld_dot);
   if (b <= 32) return launch_spmm_t<4, 16>(A, X, ldx, Y, ldy, b, s, fuse, first, beta, P, ldp, partial, dot_with, ld_dot);
+  if (!dot_with) return launch_spmm_r64(A, X, ldx, Y, ldy, b, s, fuse, first, beta, P, ldp, partial);
   return launch_spmm_t<1, 64>(A, X, ldx, Y, ldy, b, s, fuse, first, beta, P, ldp, partial, dot_with, ld_dot);
 }
 

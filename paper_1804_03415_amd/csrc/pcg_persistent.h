@@ -1,6 +1,9 @@
 // Persistent cooperative CG / flexible PCG for one right-hand side.
 #pragma once
 
+#include <vector>
+
+#include "common.h"
 #include "kernels.h"
 
 namespace mmd {
@@ -22,9 +25,20 @@ struct Pcg1Args {
   double* res = nullptr;  // [2]: final ||r||^2, ||b||^2
 };
 
+// Row partition and LDS size for the resident plain-CG kernel on A (host copy
+// rp of its row pointers).  resident == false: A does not fit, use k_pcg1.
+struct Pcg1Plan {
+  bool resident = false;
+  int grid = 0;
+  size_t lds = 0;
+  DBuf<int> part;  // grid + 1 row boundaries
+};
+void pcg1_plan(const CsrView& A, const std::vector<int>& rp, Pcg1Plan& plan);
+
 // Launch on stream s (asynchronous).  Stop rule ||r|| <= tol ||b||; the inner
-// CG stops at ||r_in|| <= tol_in ||r||.
-void pcg1(Pcg1Args a, hipStream_t s);
+// CG stops at ||r_in|| <= tol_in ||r||.  Plain CG (no M) runs the resident
+// kernel when plan says it fits.
+void pcg1(Pcg1Args a, hipStream_t s, const Pcg1Plan* plan = nullptr);
 size_t pcg1_red_size();
 int pcg1_grid();
 

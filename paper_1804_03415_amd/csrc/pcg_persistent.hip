@@ -338,6 +338,163 @@ __global__ __launch_bounds__(kThreads) void k_pcg1(Pcg1Args a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Resident plain CG (no preconditioner; the level-0 operator).  Block bx owns
+// the contiguous rows [part[bx], part[bx+1]) (balanced by nonzeros + rows on
+// the host) and keeps their slice of the matrix in LDS for the whole solve;
+// thread t owns local rows t, t + 1024, ... and holds x, r, p, q of those rows
+// in registers.  Only r goes through global memory, because neighbouring rows
+// of other blocks gather it.  The arithmetic per iteration is that of k_pcg1's
+// plain CG (q = A r + beta q, p = r + beta p, one grid sum each for p.q and
+// r.r); the sums inside a row are taken in a different order.
+constexpr int kMaxU = 4;  // rows per thread
+
+// (A r)_i of local row l with r_i = ri (edge form when ldg != null).
+__device__ inline double row_res(int l, double ri, const int* lrp, const int* lcol,
+                                 const double* lval, const double* ldg, const double* r) {
+  const int lo = lrp[l], hi = lrp[l + 1];
+  double a0 = 0.0, a1 = 0.0;
+  int k = lo;
+  if (ldg) {
+    for (; k + 3 < hi; k += 4) {
+      const double x0 = r[lcol[k]], x1 = r[lcol[k + 1]], x2 = r[lcol[k + 2]], x3 = r[lcol[k + 3]];
+      a0 += lval[k] * (ri - x0) + lval[k + 1] * (ri - x1);
+      a1 += lval[k + 2] * (ri - x2) + lval[k + 3] * (ri - x3);
+    }
+    for (; k < hi; ++k) a0 += lval[k] * (ri - r[lcol[k]]);
+    return ldg[l] * ri + (a0 + a1);
+  }
+  for (; k + 3 < hi; k += 4) {
+    const double x0 = r[lcol[k]], x1 = r[lcol[k + 1]], x2 = r[lcol[k + 2]], x3 = r[lcol[k + 3]];
+    a0 += lval[k] * x0 + lval[k + 1] * x1;
+    a1 += lval[k + 2] * x2 + lval[k + 3] * x3;
+  }
+  for (; k < hi; ++k) a0 += lval[k] * r[lcol[k]];
+  return a0 + a1;
+}
+
+__global__ __launch_bounds__(kThreads) void k_cg1_res(Pcg1Args a, const int* __restrict__ part) {
+  extern __shared__ double lds[];
+  __shared__ double sh[kThreads / kWave];
+  const int bx = (gridDim.x % 8) ? (int)blockIdx.x
+                                 : (int)((blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8);
+  Ctx c{a.bar, 0u, (int)gridDim.x, (int)blockIdx.x, 0, 0, 0, 0, (int)(threadIdx.x & (kWave - 1)),
+        a.red, 0};
+  const CsrView& A = a.A;
+  const int r0 = part[bx], r1 = part[bx + 1], nr = r1 - r0;
+  const int e0 = A.rowptr[r0], ne = A.rowptr[r1] - e0;
+  const bool edge = A.diag != nullptr;
+  double* lval = lds;
+  double* ldg = lval + ne;
+  int* lrp = reinterpret_cast<int*>(ldg + (edge ? nr : 0));
+  int* lcol = lrp + nr + 1;
+  for (int t = threadIdx.x; t < ne; t += kThreads) {
+    lval[t] = A.val[e0 + t];
+    lcol[t] = A.col[e0 + t];
+  }
+  for (int t = threadIdx.x; t <= nr; t += kThreads) lrp[t] = A.rowptr[r0 + t] - e0;
+  if (edge)
+    for (int t = threadIdx.x; t < nr; t += kThreads) ldg[t] = A.diag[r0 + t];
+  __syncthreads();
+  const double* dg = edge ? ldg : nullptr;
+  double* r = a.r;
+  double xr[kMaxU], rr_[kMaxU], pr[kMaxU], qr[kMaxU];
+  double pb = 0.0, prr0 = 0.0;
+#pragma unroll
+  for (int u = 0; u < kMaxU; ++u) {
+    xr[u] = rr_[u] = pr[u] = qr[u] = 0.0;
+    const int l = threadIdx.x + u * kThreads;
+    if (l < nr) {
+      const double bi = a.b[r0 + l];
+      pb += bi * bi;
+      if (a.use_x0) {
+        xr[u] = a.x[r0 + l];
+      } else {
+        rr_[u] = bi;
+        r[r0 + l] = bi;
+      }
+    }
+  }
+  if (a.use_x0) {
+    // r = b - A x0, x0 gathered from global memory (complete at launch)
+#pragma unroll
+    for (int u = 0; u < kMaxU; ++u) {
+      const int l = threadIdx.x + u * kThreads;
+      if (l < nr) {
+        const double ri = a.b[r0 + l] - row_res(l, xr[u], lrp, lcol, lval, dg, a.x);
+        rr_[u] = ri;
+        r[r0 + l] = ri;
+        prr0 += ri * ri;
+      }
+    }
+  } else {
+    prr0 = pb;
+  }
+  double bn2, rr2;
+  grid_sum2(c, pb, prr0, sh, bn2, rr2);
+  const double tol2 = a.tol * a.tol * bn2;
+  int it = 0, flag = 0;
+  bool done = !(bn2 > 0.0) || rr2 <= tol2;
+  double rho = rr2, beta = 0.0;
+  bool first = true;
+  while (!done) {
+    double ppq = 0.0;
+#pragma unroll
+    for (int u = 0; u < kMaxU; ++u) {
+      const int l = threadIdx.x + u * kThreads;
+      if (l < nr) {
+        const double w = row_res(l, rr_[u], lrp, lcol, lval, dg, r);
+        const double pn = first ? rr_[u] : rr_[u] + beta * pr[u];
+        const double qn = first ? w : w + beta * qr[u];
+        pr[u] = pn;
+        qr[u] = qn;
+        ppq += pn * qn;
+      }
+    }
+    first = false;
+    const double pq = grid_sum(c, ppq, sh);
+    if (!(pq > 0.0)) {
+      flag = 1;
+      break;
+    }
+    const double al = rho / pq;
+    double prr = 0.0;
+#pragma unroll
+    for (int u = 0; u < kMaxU; ++u) {
+      const int l = threadIdx.x + u * kThreads;
+      if (l < nr) {
+        xr[u] += al * pr[u];
+        const double ri = rr_[u] - al * qr[u];
+        rr_[u] = ri;
+        r[r0 + l] = ri;
+        prr += ri * ri;
+      }
+    }
+    const double rn = grid_sum(c, prr, sh);
+    ++it;
+    beta = rn / rho;
+    rho = rn;
+    rr2 = rn;
+    if (rn <= tol2) break;
+    if (it >= a.maxit) {
+      flag = 2;
+      break;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kMaxU; ++u) {
+    const int l = threadIdx.x + u * kThreads;
+    if (l < nr) a.x[r0 + l] = xr[u];
+  }
+  if (bx == 0 && threadIdx.x == 0) {
+    a.out[0] = it;
+    a.out[1] = 0;
+    a.out[2] = flag;
+    a.res[0] = rr2;
+    a.res[1] = bn2;
+  }
+}
+
 int lanes_for(double avg) {
   if (avg <= 10.0) return 8;
   if (avg <= 24.0) return 16;
@@ -365,7 +522,17 @@ int pcg1_grid() {
   return cached;
 }
 
-void pcg1(Pcg1Args a, hipStream_t s) {
+void pcg1(Pcg1Args a, hipStream_t s, const Pcg1Plan* plan) {
+  MMD_HIP(hipMemsetAsync(a.bar, 0, sizeof(unsigned), s));
+  void* args[] = {&a};
+  if (plan && plan->resident && !a.M.rowptr) {
+    const int* part = plan->part.p;
+    void* rargs[] = {&a, &part};
+    MMD_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_cg1_res),
+                                       dim3(plan->grid), dim3(kThreads), rargs,
+                                       static_cast<unsigned>(plan->lds), s));
+    return;
+  }
   // blocks: barrier cost (~30 ns per block) against memory-level parallelism
   const int64_t work = a.A.nnz + (a.M.rowptr ? a.M.nnz : 0);
   int grid = static_cast<int>(std::min<int64_t>(128, std::max<int64_t>(16, work / 16384)));
@@ -373,12 +540,65 @@ void pcg1(Pcg1Args a, hipStream_t s) {
   grid = std::min(grid, pcg1_grid());
   grid = std::min(grid, std::max(1, (a.n + kThreads - 1) / kThreads * 4));
   if (grid >= 8) grid = grid / 8 * 8;  // whole XCD rounds
-  MMD_HIP(hipMemsetAsync(a.bar, 0, sizeof(unsigned), s));
   a.lpr_a = lanes_for(a.A.avg_row);
   a.lpr_m = a.M.rowptr ? lanes_for(a.M.avg_row) : 8;
-  void* args[] = {&a};
   MMD_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_pcg1), dim3(grid),
                                      dim3(kThreads), args, 0, s));
+}
+
+void pcg1_plan(const CsrView& A, const std::vector<int>& rp, Pcg1Plan& plan) {
+  plan.resident = false;
+  const int n = A.n_rows;
+  if (n == 0 || (int)rp.size() != n + 1) return;
+  // 14 blocks per XCD measured best for the n = 1e5 RGG (barrier cost grows
+  // with the block count, the per-thread row count with fewer blocks)
+  int grid = 112;
+  if (const char* e = std::getenv("MMDEIG_RES_BLOCKS")) grid = std::max(8, std::atoi(e));
+  if (const char* e = std::getenv("MMDEIG_NO_RESIDENT"))
+    if (std::atoi(e) != 0) return;
+  grid = std::max(8, grid / 8 * 8);
+  grid = std::min(grid, std::max(8, (n + 63) / 64 / 8 * 8));
+  // balance nonzeros + rows: block j starts at the first row whose prefix
+  // weight reaches j / grid of the total
+  const double tot = static_cast<double>(rp[n]) + n;
+  std::vector<int> part(grid + 1, n);
+  part[0] = 0;
+  int i = 0;
+  for (int j = 1; j < grid; ++j) {
+    const double target = tot * j / grid;
+    while (i < n && static_cast<double>(rp[i]) + i < target) ++i;
+    part[j] = i;
+  }
+  size_t lds = 0;
+  int max_rows = 0;
+  const bool edge = A.diag != nullptr;
+  for (int j = 0; j < grid; ++j) {
+    const int nr = part[j + 1] - part[j];
+    const size_t ne = static_cast<size_t>(rp[part[j + 1]] - rp[part[j]]);
+    const size_t b = ne * 12 + (edge ? 8 * (size_t)nr : 0) + 4 * (size_t)(nr + 1);
+    lds = std::max(lds, b);
+    max_rows = std::max(max_rows, nr);
+  }
+  if (max_rows > kMaxU * kThreads) return;
+  int dev = 0;
+  MMD_HIP(hipGetDevice(&dev));
+  int maxsh = 0;
+  MMD_HIP(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  const size_t static_lds = sizeof(double) * (kThreads / kWave);
+  if (lds + static_lds > static_cast<size_t>(maxsh)) return;
+  lds = (lds + 255) / 256 * 256;
+  MMD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cg1_res),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  int per = 0;
+  MMD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cg1_res, kThreads, lds));
+  int cus = 0;
+  MMD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  if (per <= 0 || grid > per * cus) return;
+  plan.part.ensure(grid + 1);
+  MMD_HIP(hipMemcpy(plan.part.p, part.data(), sizeof(int) * (grid + 1), hipMemcpyHostToDevice));
+  plan.grid = grid;
+  plan.lds = lds;
+  plan.resident = true;
 }
 
 size_t pcg1_red_size() { return 4 * (size_t)1024; }

@@ -389,7 +389,19 @@ bool Solver::pcg_single(int k, const double* B, double* X, double tol, bool use_
   a.use_x0 = use_x0 ? 1 : 0;
   a.out = pool_.i("p1:out", 3);
   a.res = pool_.d("p1:res", 2);
-  pcg1(a, s_);
+  const Pcg1Plan* plan = nullptr;
+  if (k == 0) {
+    auto it = plans_.find(k);
+    if (it == plans_.end()) {
+      std::vector<int> rp(n + 1);
+      d2h(rp.data(), a.A.rowptr, n + 1);
+      sync();
+      it = plans_.emplace(k, Pcg1Plan()).first;
+      pcg1_plan(a.A, rp, it->second);
+    }
+    plan = &it->second;
+  }
+  pcg1(a, s_, plan);
   hi_.ensure(4);
   d2h(hi_.p, a.out, 3);
   sync();

@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "handle.h"
+#include "pcg_persistent.h"
 
 namespace mmd {
 
@@ -107,6 +108,7 @@ class Solver {
   HBuf<int> hi_;
   int inner_iters_ = 16;
   bool use_persistent_ = true;
+  std::map<int, Pcg1Plan> plans_;  // resident plain-CG plan per level (level 0)
   int cur_level_ = 0;
   int64_t draws_[MMD_MAX_LEVELS] = {};
 };
