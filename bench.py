@@ -34,12 +34,16 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=100000)
     ap.add_argument("--nev", type=int, default=300)
     ap.add_argument("--tol", type=float, default=1e-9)
     ap.add_argument("--levels", type=int, default=3)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32-refine"])
+    ap.add_argument("--mixed-steps", type=int, default=1,
+                    help="timed eigensolves of the FP32-CG + FP64-refinement form after the "
+                         "main run (0: skip), compared pair by pair with the main run")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample-frac", type=float, default=0.05)
     ap.add_argument("--traffic-bytes", type=float, default=None,
@@ -49,6 +53,45 @@ def parse():
                     help="only copy a MIB-sized device buffer 5 times (the reference kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings) and exit")
     return ap.parse_args()
+
+
+def cluster_angles(lam, V, W, gap=1e-6):
+    """Largest principal angle per cluster of lam (relative gap < 1e-6) between
+    the column spans of V and W, as ||W_c - V_c (V_c^T W_c)||_2."""
+    out = []
+    i = 0
+    while i < lam.size:
+        j = i + 1
+        while j < lam.size and (lam[j] - lam[j - 1]) / lam[j - 1] < gap:
+            j += 1
+        Vc, Wc = V[:, i:j], W[:, i:j]
+        out.append(np.linalg.norm(Wc - Vc @ (Vc.T @ Wc), 2))
+        i = j
+    return np.array(out)
+
+
+def timed_solves(dec, a, precision, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        dec.eig_leftmost(a.nev, tol=a.tol, precision=precision)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for _ in range(steps):
+        lam, V, st = dec.eig_leftmost(a.nev, tol=a.tol, precision=precision)
+        stats.append(st)
+    torch.cuda.synchronize()
+    return lam, V, stats, time.perf_counter() - t0
+
+
+def kernel_roofline(stats):
+    launches = sum(s_["spmm0"]["launches"] for s_ in stats)
+    ms_tot = sum(s_["spmm0"]["ms"] for s_ in stats)
+    bytes_tot = sum(s_["spmm0"]["bytes"] for s_ in stats)
+    achieved = bytes_tot / max(ms_tot * 1e-3, 1e-12) / 1e9
+    return dict(achieved=round(achieved, 1), frac=round(achieved / HBM_PEAK_GBS, 4),
+                bytes_per_launch=round(bytes_tot / max(launches, 1)), launches=launches,
+                avg_launch_us=round(1000.0 * ms_tot / max(launches, 1), 2))
 
 
 def measured_traffic():
@@ -118,44 +161,56 @@ def main():
     info = dec.info()
     if a.verbose:
         print("decomposition", info, "build %.2fs" % t_build, file=sys.stderr, flush=True)
-    for w in range(a.warmup):
-        lam, V, st = dec.eig_leftmost(a.nev, tol=a.tol)
-        if a.verbose:
-            print("warmup %d: %.3fs" % (w, st["seconds_total"]), file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = []
-    for s in range(a.steps):
-        lam, V, st = dec.eig_leftmost(a.nev, tol=a.tol)
-        stats.append(st)
-        if a.verbose:
-            print("step %d: %.3fs" % (s, st["seconds_total"]), file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    lam, V, stats, elapsed = timed_solves(dec, a, a.precision, a.steps, a.warmup)
     ms_step = 1000.0 * elapsed / a.steps
     value = a.nev * a.steps / elapsed
+    if a.verbose:
+        print(json.dumps(stats[-1]), file=sys.stderr, flush=True)
 
     # acceptance: every returned pair meets the residual target (FP64, CSR form)
     A = p.scipy()
     Vh = V.cpu().numpy().T
-    rho = np.linalg.norm(A @ Vh - Vh * lam[None, :], axis=0) / (np.abs(lam) * np.linalg.norm(Vh, axis=0))
+
+    def residuals(lam_, Vh_):
+        return np.linalg.norm(A @ Vh_ - Vh_ * lam_[None, :], axis=0) / (
+            np.abs(lam_) * np.linalg.norm(Vh_, axis=0))
+
+    rho = residuals(lam, Vh)
     ncomp_null = int(np.sum(np.abs(lam - 1e-6) < 1e-12))
 
     # dominant kernel: the level-0 fused SpMM of the refinement block CG, timed by
     # the library with HIP events on the solve's stream over the timed steps
-    launches = sum(s_["spmm0"]["launches"] for s_ in stats)
-    ms_tot = sum(s_["spmm0"]["ms"] for s_ in stats)
-    bytes_tot = sum(s_["spmm0"]["bytes"] for s_ in stats)
-    avg_us = 1000.0 * ms_tot / max(launches, 1)
-    achieved = bytes_tot / max(ms_tot * 1e-3, 1e-12) / 1e9
-    traffic = a.traffic_bytes if a.traffic_bytes is not None else measured_traffic()
+    kr = kernel_roofline(stats)
+    fp32 = a.precision == "fp32-refine"
+    traffic = a.traffic_bytes if a.traffic_bytes is not None else (
+        None if fp32 else measured_traffic())
     roof = {"bound": "hbm",
-            "kernel": "k_spmm_r64<edge,fuse>: level-0 block-CG step P = R + beta P, "
-                      "Q = A R + beta Q, partial p.q (block width %d..1)" % a.nev,
-            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "bytes_per_launch": round(bytes_tot / max(launches, 1)), "launches": launches,
-            "avg_launch_us": round(avg_us, 2)}
+            "kernel": ("k_spmm32_w<edge>: level-0 FP32 block-CG step" if fp32 else
+                       "k_spmm_r64<edge,fuse>: level-0 block-CG step P = R + beta P, "
+                       "Q = A R + beta Q, partial p.q") + " (block width %d..1)" % a.nev,
+            "achieved": kr["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": kr["frac"], "traffic": traffic,
+            "bytes_per_launch": kr["bytes_per_launch"], "launches": kr["launches"],
+            "avg_launch_us": kr["avg_launch_us"]}
+
+    mixed = None
+    if a.mixed_steps > 0 and not fp32:
+        lm, Vm, stm, el_m = timed_solves(dec, a, "fp32-refine", a.mixed_steps, 1)
+        Vmh = Vm.cpu().numpy().T
+        rho_m = residuals(lm, Vmh)
+        ang = cluster_angles(lam, Vh, Vmh)
+        krm = kernel_roofline(stm)
+        mixed = {"value": round(a.nev * a.mixed_steps / el_m, 3),
+                 "ms_per_step": round(1000.0 * el_m / a.mixed_steps, 2),
+                 "steps": a.mixed_steps, "warmup": 1,
+                 "max_rel_residual": float(rho_m.max()),
+                 "residual_ok": bool(rho_m.max() <= 1e-8),
+                 "max_rel_eig_err_vs_fp64": float(np.max(np.abs(lm - lam) / lam)),
+                 "max_cluster_angle_vs_fp64": float(ang.max()),
+                 "kernel": "k_spmm32_w<edge>: level-0 FP32 block-CG step",
+                 "kernel_achieved_GBs": krm["achieved"], "kernel_frac": krm["frac"],
+                 "kernel_avg_launch_us": krm["avg_launch_us"],
+                 "kernel_launches": krm["launches"]}
 
     cpu = None
     if a.cpu_baseline:
@@ -176,7 +231,7 @@ def main():
                "sample_rate": round(v_s, 4)}
 
     out = {
-        "metric": "eigenpairs/s at rel. residual 1e-8 (FP64)",
+        "metric": "eigenpairs/s at rel. residual 1e-8",
         "value": round(value, 3),
         "unit": "eigenpairs/s",
         "n_gpus": 1,
@@ -186,7 +241,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if fp32 else "f64",
         "data": "synthetic",
         "config": {"workload": "rgg_laplacian_n%d_nev%d" % (a.n, a.nev), "n": a.n,
                    "nnz": int(p.nnz), "nev": a.nev, "tol": a.tol,
@@ -196,9 +251,8 @@ def main():
         "null_cluster": ncomp_null,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "fp32_refine": mixed,
     }
-    if a.verbose:
-        print(json.dumps(stats[-1]), file=sys.stderr)
     print(json.dumps(out), flush=True)
 
 

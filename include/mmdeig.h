@@ -75,7 +75,11 @@ typedef struct {
   double alpha;            /* mu_re^(k) = alpha eps_{k+1} [3]                    */
   double beta;             /* mu_ex^(k) = beta eps_k [1]                         */
   int32_t restart_mult;    /* c: shifts per restart = c d [1]                    */
-  int32_t reserved;
+  int32_t precision;       /* 0: FP64 throughout [0].  1: level-0 block solves
+                              run CG in FP32 (FP32 matrix copy and vectors)
+                              inside an FP64 iterative refinement (residual,
+                              update and stop test in FP64, same tolerance);
+                              everything else stays FP64                      */
   uint64_t seed;           /* Philox key of the random start vectors [0]         */
   int32_t max_restarts;    /* per extension [2000]                               */
   int32_t max_refine;      /* refinement iterations per level [200]              */
@@ -166,7 +170,9 @@ int mmd_apply(mmd_handle* h, int32_t level, int32_t op, const double* X, double*
 /* Column-wise solves on one level, b independent right-hand sides (device,
  * row-major, leading dimension b).  kind 0: pcg(A^(k), rhs, M^(k), x0, tol)
  * of Section 4 (flexible PCG with an inner CG on M^(k) to 0.1 tol; plain CG on
- * level 0); kind 1: cg(B^(k+1), rhs, -, x0, tol) (Alg. 5 start block).  X holds
+ * level 0); kind 1: cg(B^(k+1), rhs, -, x0, tol) (Alg. 5 start block);
+ * kind 2 (level 0 only): the same solve as kind 0 by FP32 CG inside an FP64
+ * iterative refinement (the precision = 1 form of eig_opts).  X holds
  * x0 on entry (use_x0 != 0) and the solution on exit.  iters (host int32[b],
  * may be NULL) receives the outer iteration counts. */
 int mmd_solve(mmd_handle* h, int32_t level, int32_t kind, const double* rhs, double* X,

@@ -41,7 +41,7 @@ class mmd_build_opts(ctypes.Structure):
 
 class eig_opts(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double),
-                ("restart_mult", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("restart_mult", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("max_restarts", ctypes.c_int32),
                 ("max_refine", ctypes.c_int32)]
 

@@ -30,10 +30,15 @@ def build_options(levels=3, targets=(4, 8), grid_blocks=(4, 2), r_hops=1, exact_
 
 
 def solver_options(alpha=3.0, beta=1.0, restart_mult=1, seed=0, max_restarts=2000,
-                   max_refine=200):
+                   max_refine=200, precision="fp64"):
+    """eig_opts; precision "fp64" or "fp32-refine" (FP32 CG inside FP64
+    iterative refinement for the level-0 block solves)."""
     o = eig_opts()
     o.alpha, o.beta, o.restart_mult, o.seed = alpha, beta, restart_mult, seed
     o.max_restarts, o.max_refine = max_restarts, max_refine
+    if precision not in ("fp64", "fp32-refine"):
+        raise ValueError("precision must be 'fp64' or 'fp32-refine'")
+    o.precision = 0 if precision == "fp64" else 1
     return o
 
 
@@ -120,7 +125,8 @@ class Decomposition:
         return s[level] - s[level + 1]  # B and U^T map into the reduced space
 
     def solve(self, level, kind, rhs, x0=None, tol=1e-10, stream=None):
-        """Column-wise PCG on A^(k) (kind 0) or CG on B^(k+1) (kind 1); returns (X, iters)."""
+        """Column-wise PCG on A^(k) (kind 0), CG on B^(k+1) (kind 1) or the level-0
+        solve by FP32 CG inside FP64 iterative refinement (kind 2); returns (X, iters)."""
         import torch
         rhs = rhs.contiguous()
         b = rhs.shape[1]

@@ -8,6 +8,7 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "mixed.h"
 
 namespace mmd {
 
@@ -42,6 +43,10 @@ struct LevelDev {
   DBuf<double> a_val, a_diag, m_val, p_val, h_u, h_scale;
   CsrView A, M, Psi;
   HouseView H;  // transfer (k-1 -> k): U^(k)
+  // FP32 copy of A (level 0, mixed precision), made on first use
+  DBuf<float> a_val32, a_diag32;
+  CsrView32 A32;
+  bool has32 = false;
 };
 
 }  // namespace mmd

@@ -104,6 +104,8 @@ void zero_block(double* Y, int ldy, int n, int b, hipStream_t s);
 // Y = X * diag(d) (+ Y if accumulate)
 void scale_cols(const double* X, int ldx, const double* d, double* Y, int ldy, int n, int b,
                 bool accumulate, hipStream_t s);
+// X(i, c) *= d[i]  (n x b)
+void scale_rows(double* X, int ldx, const double* d, int n, int b, hipStream_t s);
 // Y = a X + c Y   (scalars on host)
 void axpby(double a, const double* X, int ldx, double c, double* Y, int ldy, int n, int b,
            hipStream_t s);

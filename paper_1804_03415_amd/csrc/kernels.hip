@@ -598,6 +598,14 @@ __global__ void k_xpay(const double* __restrict__ R, int ldr, double* __restrict
   P[i * ldp + c] = first ? r : r + beta[c] * P[i * ldp + c];
 }
 
+__global__ void k_scale_rows(double* __restrict__ X, int ldx, const double* __restrict__ d, int n,
+                             int b) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * b) return;
+  const int64_t i = t / b, c = t % b;
+  X[i * ldx + c] *= d[i];
+}
+
 __global__ void k_copy(const double* __restrict__ X, int ldx, double* __restrict__ Y, int ldy,
                        int n, int b) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -988,6 +996,13 @@ int cg_update(double* X, int ldx, double* R, const double* P, const double* Q, i
                      partial);
   check_launch();
   return g;
+}
+
+void scale_rows(double* X, int ldx, const double* d, int n, int b, hipStream_t s) {
+  if ((int64_t)n * b == 0) return;
+  hipLaunchKernelGGL(k_scale_rows, dim3(ew_grid((int64_t)n * b)), dim3(kBlock), 0, s, X, ldx, d,
+                     n, b);
+  check_launch();
 }
 
 void xpay(const double* R, int ldr, double* P, int ldp, int n, int b, const double* beta,

@@ -17,6 +17,7 @@
 #include <numeric>
 
 #include "dense.h"
+#include "mixed.h"
 #include "pcg_persistent.h"
 
 namespace mmd {
@@ -412,15 +413,234 @@ bool Solver::pcg_single(int k, const double* B, double* X, double tol, bool use_
   return true;
 }
 
+// ------------------------------------------------------------------ mixed precision
+void Solver::ensure32() {
+  LevelDev& D = h_.dev[0];
+  if (D.has32) return;
+  const CsrView& A = D.A;
+  D.a_val32.ensure(std::max<int64_t>(1, A.nnz));
+  to_f32(A.val, D.a_val32.p, A.nnz, s_);
+  if (A.diag) {
+    D.a_diag32.ensure(std::max(1, A.n_rows));
+    to_f32(A.diag, D.a_diag32.p, A.n_rows, s_);
+  }
+  D.A32.n_rows = A.n_rows;
+  D.A32.n_cols = A.n_cols;
+  D.A32.nnz = A.nnz;
+  D.A32.rowptr = A.rowptr;
+  D.A32.col = A.col;
+  D.A32.val = D.a_val32.p;
+  D.A32.diag = A.diag ? D.a_diag32.p : nullptr;
+  D.has32 = true;
+}
+
+void Solver::cg32(float* R32, int m, const std::vector<int>& gcols, double* X, int ldx,
+                  double eta, std::vector<int>& its) {
+  const int n = nlev(0);
+  const CsrView32& A = h_.dev[0].A32;
+  int bc = m, ldw = even_ld(m);
+  ColScalars sc = make_scalars(pool_, "m32", m);
+  float* R = R32;
+  float* P = pool_.f("m32:P", (size_t)n * ldw);
+  float* Q = pool_.f("m32:Q", (size_t)n * ldw);
+  float* D = pool_.f("m32:D", (size_t)n * ldw);
+  double* p1 = pool_.d("m32:p1", (size_t)kRedBlocks * m);
+  double* p2 = pool_.d("m32:p2", (size_t)kRedBlocks * m);
+  int* d_src = pool_.i("m32:src", m);
+  int* d_dst = pool_.i("m32:dst", m);
+  zero32(D, n, ldw, s_);
+  zero32(P, n, ldw, s_);
+  zero32(Q, n, ldw, s_);
+  const int nb = col_dot32(R, ldw, R, ldw, n, bc, p1, s_);
+  cg_init(sc, p1, nullptr, nb, bc, eta, nullptr, s_);
+  MMD_HIP(hipMemsetAsync(sc.notspd, 0, sizeof(int), s_));
+  std::vector<int> cols(m);
+  for (int j = 0; j < m; ++j) cols[j] = j;  // working column -> local column
+  its.assign(m, 0);
+  // add working columns src (working index) to X(:, gcols[cols[src]])
+  auto flush = [&](const std::vector<int>& src) {
+    if (src.empty()) return;
+    std::vector<int> dst(src.size());
+    for (size_t j = 0; j < src.size(); ++j) dst[j] = gcols[cols[src[j]]];
+    h2d(d_src, src.data(), src.size());
+    h2d(d_dst, dst.data(), dst.size());
+    scatter_add64(D, ldw, d_src, d_dst, X, ldx, n, static_cast<int>(src.size()), s_);
+    sync();  // the host index lists must outlive the copies
+  };
+  auto take_iters = [&]() {
+    hi_.ensure(bc);
+    d2h(hi_.p, sc.iters, bc);
+    sync();
+    for (int c = 0; c < bc; ++c) its[cols[c]] = hi_.p[c];
+  };
+  auto iterate = [&](bool first) {
+    const bool timed = bc > 64;
+    if (timed) spmm0_begin();
+    const int np = spmm32_cg(A, R, ldw, Q, ldw, bc, first, sc.beta, P, ldw, p1, s_);
+    if (timed) {
+      // matrix once (4-byte weights and columns, row pointers, self-loops),
+      // R read once, P and Q read and written once (FP32)
+      const double nnz = static_cast<double>(A.nnz);
+      const double bytes = 8.0 * nnz + 8.0 * n + 20.0 * n * static_cast<double>(bc) +
+                           (first ? -8.0 * n * static_cast<double>(bc) : 0.0);
+      spmm0_end(bytes, bc);
+    }
+    cg_alpha(sc, p1, np, bc, s_);
+    const int nu = cg_update32(D, ldw, R, P, Q, ldw, n, bc, sc.alpha, p2, s_);
+    cg_beta(sc, p2, nu, bc, s_);
+  };
+  // FP32 CG cannot push the residual far below its rounding level; the outer
+  // FP64 loop measures the true progress, so the inner solve just stops at
+  // the cap
+  const int maxit = 4 * n + 1000;
+  int done = 0, chunk = 4, stage = 0;
+  bool first = true;
+  while (true) {
+    for (int t = 0; t < chunk; ++t) {
+      iterate(first);
+      first = false;
+    }
+    done += chunk;
+    hi_.ensure(bc + 1);
+    d2h(hi_.p, sc.active, bc);
+    d2h(hi_.p + bc, sc.notspd, 1);
+    sync();
+    MMD_REQUIRE(hi_.p[bc] == 0, MMD_ENOTSPD, "CG curvature p^T A p <= 0 (FP32)");
+    std::vector<int> keep, drop;
+    for (int c = 0; c < bc; ++c) (hi_.p[c] != 0 ? keep : drop).push_back(c);
+    if (keep.empty() || done >= maxit) break;
+    chunk = std::min(chunk * 2, 64);
+    const int na = static_cast<int>(keep.size());
+    if (bc >= 16 && 4 * na <= 3 * bc) {
+      take_iters();
+      flush(drop);
+      ++stage;
+      const std::string st = "m32:c" + std::to_string(stage & 1);
+      const int ld2 = even_ld(na);
+      float* R2 = pool_.f(st + "R", (size_t)n * ld2);
+      float* P2 = pool_.f(st + "P", (size_t)n * ld2);
+      float* Q2 = pool_.f(st + "Q", (size_t)n * ld2);
+      float* D2 = pool_.f(st + "D", (size_t)n * ld2);
+      ColScalars sc2 = make_scalars(pool_, st, m);
+      sc2.notspd = sc.notspd;
+      h2d(d_src, keep.data(), na);
+      gather32(R, ldw, d_src, R2, ld2, n, na, s_);
+      gather32(P, ldw, d_src, P2, ld2, n, na, s_);
+      gather32(Q, ldw, d_src, Q2, ld2, n, na, s_);
+      gather32(D, ldw, d_src, D2, ld2, n, na, s_);
+      gather_scalars(sc, sc2, d_src, na, s_);
+      sync();  // keep (host) must outlive its copy
+      std::vector<int> cols2(na);
+      for (int j = 0; j < na; ++j) cols2[j] = cols[keep[j]];
+      cols.swap(cols2);
+      R = R2;
+      P = P2;
+      Q = Q2;
+      D = D2;
+      ldw = ld2;
+      sc = sc2;
+      bc = na;
+    }
+  }
+  take_iters();
+  std::vector<int> all(bc);
+  for (int c = 0; c < bc; ++c) all[c] = c;
+  flush(all);
+}
+
+void Solver::cg_mixed(const double* B, int ldb, double* X, int ldx, int b, double tol,
+                      bool use_x0, std::vector<int>* iters, const Deflation* dfl) {
+  const int n = nlev(0);
+  ensure32();
+  double* R = pool_.d("mx:R", (size_t)n * b);
+  double* part = pool_.d("mx:part", (size_t)kRedBlocks * b);
+  double* nrm = pool_.d("mx:nrm", b);
+  int* d_idx = pool_.i("mx:idx", b);
+  if (!use_x0) zero_block(X, ldx, n, b, s_);
+  auto col_norms = [&](const double* Y, int ldy, std::vector<double>& out) {
+    const int g = col_dot(Y, ldy, Y, ldy, n, b, part, s_);
+    reduce_partials(part, g, b, nrm, s_);
+    out.resize(b);
+    d2h(out.data(), nrm, b);
+    sync();
+  };
+  std::vector<double> bn2, rr;
+  col_norms(B, ldb, bn2);
+  std::vector<int> total(b, 0), its;
+  std::vector<char> live(b, 1);
+  std::vector<double> prev(b, 0.0);
+  // inner FP32 solves reduce the residual by eta each; the true FP64 residual
+  // decides convergence: ||r|| <= tol ||b||, or a column whose residual no
+  // longer halves per refinement step has reached the FP64 floor
+  // u ||A|| ||x|| of a true residual (the recursive residual of FP64 CG has
+  // no such floor, so tight tolerances on near-singular systems end here)
+  // eta = 1e-2 measured best on the n = 1e5 RGG (1e-1 .. 1e-6 tried): FP32 CG
+  // slows down sharply when pushed deep, restarts are cheap
+  const double eta = 1e-2;
+  const int max_outer = 60;
+  // ||A||_inf of the level-0 matrix for the floor test
+  if (norm_a0_ <= 0.0) {
+    const HostCSR& A0 = h_.host[0].A;
+    for (int i = 0; i < A0.n_rows; ++i) {
+      double t = 0.0;
+      for (int64_t q = A0.ptr[i]; q < A0.ptr[i + 1]; ++q) t += std::fabs(A0.val[q]);
+      norm_a0_ = std::max(norm_a0_, t);
+    }
+  }
+  std::vector<double> xx;
+  for (int outer = 0;; ++outer) {
+    applyA(0, X, ldx, R, b, b);
+    rsub(B, ldb, R, b, n, b, s_);
+    col_norms(R, b, rr);
+    col_norms(X, ldx, xx);
+    std::vector<int> act;
+    for (int c = 0; c < b; ++c) {
+      if (!live[c]) continue;
+      const double floor = 64.0 * 2.2e-16 * norm_a0_ * std::sqrt(xx[c]);
+      const bool stalled = outer > 0 && rr[c] > 0.25 * prev[c] && rr[c] <= floor * floor;
+      if (!(bn2[c] > 0.0) || rr[c] <= tol * tol * bn2[c] || stalled)
+        live[c] = 0;
+      else
+        act.push_back(c);
+      prev[c] = rr[c];
+    }
+    if (act.empty()) break;
+    MMD_REQUIRE(outer < max_outer, MMD_ENOCONV,
+                "mixed-precision refinement did not reach the tolerance");
+    if (dfl && dfl->m > 0) {
+      // C = Q^T R ; R -= Q C ; X += Q diag(mu) C   (all FP64)
+      const int mq = dfl->m;
+      double* C = pool_.d("mx:C", (size_t)mq * b);
+      double* gw = pool_.d("mx:gw", gram_work_size(n, mq, b));
+      gram(dfl->Q, dfl->ld, R, b, n, mq, b, C, b, gw, s_);
+      gemm_nn(dfl->Q, dfl->ld, C, b, R, b, n, mq, b, -1.0, 1.0, s_);
+      scale_rows(C, b, dfl->mu, mq, b, s_);
+      gemm_nn(dfl->Q, dfl->ld, C, b, X, ldx, n, mq, b, 1.0, 1.0, s_);
+    }
+    const int m = static_cast<int>(act.size());
+    const int ld32 = even_ld(m);
+    float* R32 = pool_.f("mx:R32", (size_t)n * ld32);
+    h2d(d_idx, act.data(), m);
+    gather_to32(R, b, d_idx, R32, ld32, n, m, s_);
+    sync();  // act (host) must outlive its copy
+    cg32(R32, m, act, X, ldx, eta, its);
+    for (int j = 0; j < m; ++j) total[act[j]] += its[j];
+  }
+  if (iters) *iters = total;
+}
+
 void Solver::pcg(int k, const double* B, int ldb, double* X, int ldx, int b, double tol,
-                 bool use_x0, std::vector<int>* iters) {
+                 bool use_x0, std::vector<int>* iters, const Deflation* dfl) {
   const int n = nlev(k);
   if (b == 1 && ldb == 1 && ldx == 1 && use_persistent_) {
     pcg_single(k, B, X, tol, use_x0, iters);
     return;
   }
   if (k == 0) {
-    cg(0, OpKind::A, B, ldb, X, ldx, n, b, tol, use_x0, nullptr, 0, "cg0", iters);
+    if (o_.precision == 1)
+      cg_mixed(B, ldb, X, ldx, b, tol, use_x0, iters, dfl);
+    else
+      cg(0, OpKind::A, B, ldb, X, ldx, n, b, tol, use_x0, nullptr, 0, "cg0", iters);
     return;
   }
   if (b == 0) return;
@@ -892,7 +1112,12 @@ void Solver::refine(int k, double*& V, std::vector<double>& D, int& m, double ep
     std::vector<int> its;
     {
       PhaseTimer pt(st_, 0, s_);
-      pcg(k, W, ml, F2, ml, ml, eps_solve, true, st_ ? &its : nullptr);
+      Deflation dfl;  // used by the mixed-precision level-0 solve only
+      dfl.Q = Q;
+      dfl.ld = ml;
+      dfl.m = ml;
+      dfl.mu = Dd;
+      pcg(k, W, ml, F2, ml, ml, eps_solve, true, st_ ? &its : nullptr, &dfl);
     }
     if (st_) {
       st_->pcg_A_calls[k] += ml;
@@ -1149,6 +1374,19 @@ void Solver::solve(int level, int kind, const double* rhs, double* X, int b, boo
       permute_rows(x, b, X, b, n0, b, h_.d_perm.p, true, s_);
     } else {
       pcg(level, rhs, b, X, b, b, tol, use_x0, &it);
+    }
+  } else if (kind == 2) {
+    MMD_REQUIRE(level == 0, MMD_EINVAL, "the mixed-precision solve is a level-0 solve");
+    const int n0 = nlev(0);
+    if (!h_.perm.empty()) {
+      double* r = pool_.d("sv:rhs", (size_t)n0 * b);
+      double* x = pool_.d("sv:x", (size_t)n0 * b);
+      permute_rows(rhs, b, r, b, n0, b, h_.d_perm.p, false, s_);
+      if (use_x0) permute_rows(X, b, x, b, n0, b, h_.d_perm.p, false, s_);
+      cg_mixed(r, b, x, b, b, tol, use_x0, &it);
+      permute_rows(x, b, X, b, n0, b, h_.d_perm.p, true, s_);
+    } else {
+      cg_mixed(rhs, b, X, b, b, tol, use_x0, &it);
     }
   } else if (kind == 1) {
     MMD_REQUIRE(level < h_.K, MMD_EINVAL, "B needs a coarser level");

@@ -15,10 +15,12 @@ class Pool {
  public:
   double* d(const std::string& name, size_t count) { return dbl_[name].ensure(count), dbl_[name].p; }
   int* i(const std::string& name, size_t count) { return int_[name].ensure(count), int_[name].p; }
+  float* f(const std::string& name, size_t count) { return flt_[name].ensure(count), flt_[name].p; }
 
  private:
   std::map<std::string, DBuf<double>> dbl_;
   std::map<std::string, DBuf<int>> int_;
+  std::map<std::string, DBuf<float>> flt_;
 };
 
 struct SolveResult {
@@ -55,10 +57,25 @@ class Solver {
   void cg(int k, OpKind op, const double* B, int ldb, double* X, int ldx, int n, int b,
           double tol, bool use_x0, const int* parent_active, int fixed_iters,
           const std::string& tag, std::vector<int>* iters);
+  // approximate eigenpairs (A q_j ~ q_j / mu_j) removed from the residual in
+  // FP64 before each FP32 inner solve of the mixed-precision form
+  struct Deflation {
+    const double* Q = nullptr;  // n x m, row-major, leading dimension ld
+    int ld = 0, m = 0;
+    const double* mu = nullptr;  // device [m]
+  };
   void pcg(int k, const double* B, int ldb, double* X, int ldx, int b, double tol, bool use_x0,
-           std::vector<int>* iters);
+           std::vector<int>* iters, const Deflation* dfl = nullptr);
   bool pcg_single(int k, const double* B, double* X, double tol, bool use_x0,
                   std::vector<int>* iters);
+  // level-0 block solve by FP32 CG inside FP64 iterative refinement
+  void cg_mixed(const double* B, int ldb, double* X, int ldx, int b, double tol, bool use_x0,
+                std::vector<int>* iters, const Deflation* dfl = nullptr);
+  // FP32 CG (zero start) on the m columns of R32 (leading dimension even_ld(m),
+  // consumed as the residual); the solutions are added to X(:, gcols[j]).
+  void cg32(float* R32, int m, const std::vector<int>& gcols, double* X, int ldx, double eta,
+            std::vector<int>& its);
+  void ensure32();
 
   // Lanczos / extension / refinement
   struct Lanczos;
@@ -109,6 +126,7 @@ class Solver {
   int inner_iters_ = 16;
   bool use_persistent_ = true;
   std::map<int, Pcg1Plan> plans_;  // resident plain-CG plan per level (level 0)
+  double norm_a0_ = 0.0;           // ||A||_inf of level 0 (mixed-precision floor test)
   int cur_level_ = 0;
   int64_t draws_[MMD_MAX_LEVELS] = {};
 };

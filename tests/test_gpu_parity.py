@@ -148,11 +148,42 @@ def test_level_solves(built, torch_cuda, b):
             assert np.all(res <= 1.5 * tol + floor)
 
 
+@pytest.mark.parametrize("b", [3, 70])
+def test_level0_mixed_solve(built, torch_cuda, b):
+    """FP32 CG inside FP64 iterative refinement (solve kind 2): the FP64 true
+    residual meets the same stop rule as the FP64 solve, and the FP32 inner
+    iterations stay within a bounded multiple of the FP64 CG iterations (a
+    wrong FP32 operator would still converge through the FP64 loop, only
+    slowly).  Without a deflation basis, random right-hand sides of the
+    near-singular graph Laplacians (shift 1e-6) cost FP32 CG several times the
+    FP64 iterations: rounding at the FP32 level keeps re-exciting the
+    near-null components.
+    b = 3 runs the narrow FP32 SpMM, b = 70 the 128-column form and column
+    compaction."""
+    torch = torch_cuda
+    p, kw, dec, M = built
+    tol = 1e-10
+    Ad = p.scipy()
+    rhs = wl.random_block(p.n, b, seed=50 + b)
+    X, it = dec.solve(0, 2, _t(torch, rhs), tol=tol)
+    X = X.cpu().numpy()
+    nb = np.linalg.norm(rhs, axis=0)
+    floor = 50 * 2.2e-16 * sla.norm(Ad.toarray(), 2) * np.linalg.norm(X, axis=0) / nb
+    res = np.linalg.norm(rhs - Ad @ X, axis=0) / nb
+    assert np.all(res <= 1.5 * tol + floor)
+    X64, it64 = dec.solve(0, 0, _t(torch, rhs), tol=tol)
+    X64 = X64.cpu().numpy()
+    cond = np.linalg.cond(Ad.toarray()) if p.n <= 4096 else 1e8
+    err = np.linalg.norm(X - X64, axis=0) / np.linalg.norm(X64, axis=0)
+    assert np.all(err <= 3 * tol * cond)
+    assert np.all(it <= 8 * it64 + 100)
+
+
 # ------------------------------------------------------------------- eigensolver
-def _run_both(p, nev, tol, kw):
+def _run_both(p, nev, tol, kw, precision="fp64"):
     from paper_1804_03415_amd import Decomposition
     dec = Decomposition.from_problem(p, **kw)
-    lam, V, st = dec.eig_leftmost(nev, tol=tol)
+    lam, V, st = dec.eig_leftmost(nev, tol=tol, precision=precision)
     okw = dict(kw)
     okw["coords"] = None if p.grid else p.coords
     okw["grid"] = p.grid
@@ -195,3 +226,31 @@ def test_eig_small(torch_cuda, case):
     full = [i for i, c in enumerate(cl) if c[-1] < nev - 1]
     assert ang[full].max() < 1e-8
     assert dense.rel_residuals(A, lam, V).max() < 1e-8
+
+
+@pytest.mark.parametrize("case", ["c1_grid", "rgg"])
+def test_eig_mixed(torch_cuda, case):
+    """precision fp32-refine: the same bars against the oracle as the FP64 mode,
+    and per-eigenpair agreement with the FP64 GPU run."""
+    if case == "c1_grid":
+        p, nev, tol, kw = wl.grid2d(32), 50, 1e-10, dict(levels=3, exact_max_n=4096)
+    else:
+        p, nev, tol, kw = wl.rgg(400, 11, mean_degree=5), 30, 1e-11, dict(levels=2)
+    lam, V, st, lo, Vo = _run_both(p, nev, tol, kw, precision="fp32-refine")
+    A = p.scipy()
+    null = np.abs(lo - 1e-6) < 1e-12
+    assert np.sum(np.abs(lam - 1e-6) < 1e-12) == np.sum(null)
+    assert np.max(np.abs(lam[~null] - lo[~null]) / lo[~null]) < 1e-10
+    if case == "c1_grid":
+        ref = _closed_2d(32, 50)
+        assert np.max(np.abs(lam - ref) / ref) < 1e-10
+    ang, cl = dense.cluster_angles(lo, Vo, V)
+    full = [i for i, c in enumerate(cl) if c[-1] < nev - 1]
+    assert ang[full].max() < 1e-8
+    assert dense.rel_residuals(A, lam, V).max() < 1e-8
+    from paper_1804_03415_amd import Decomposition
+    dec = Decomposition.from_problem(p, **kw)
+    l64, V64, _ = dec.eig_leftmost(nev, tol=tol)
+    assert np.max(np.abs(lam - l64) / l64) < 1e-10
+    a64, _ = dense.cluster_angles(l64, V64.cpu().numpy().T, V)
+    assert a64[full].max() < 1e-8
