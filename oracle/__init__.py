@@ -17,6 +17,10 @@ Modules and the passages of the paper they follow:
   krylov   CG / flexible PCG (Sec. 4, operator OP), general Lanczos with the
            M inner product (Alg. 3), implicit restart (Alg. 2), extension
            (Alg. 4), refinement (Alg. 5) and the level driver (Alg. 6).
+  backward first-order perturbation gradient of the leftmost eigenpairs with
+           respect to the stored entries of A (eigenvalue outer products,
+           eigenvector adjoints by a CG solve on the complement of the
+           computed eigenvectors); the paper gives no derivative.
   dense    the plain definition of the result (dense symmetric eigensolve)
            and per-eigenpair error measures.
   backward gradient of eigenvalues / eigenvector functionals w.r.t. A.
