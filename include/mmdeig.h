@@ -158,6 +158,28 @@ int mmd_export(const mmd_handle* h, int32_t level, int32_t which, int64_t* n_row
 int eig_leftmost(mmd_handle* h, int32_t nev, double tol, const eig_opts* opts,
                  double* evals, double* evecs, eig_stats* st, void* hip_stream);
 
+/* Reverse-mode derivative of the nev leftmost eigenpairs (the paper gives
+ * none; first-order perturbation of a symmetric matrix).  Given the pairs
+ * returned by eig_leftmost (evals host [nev] ascending, evecs device
+ * column-major n x nev, orthonormal) and the adjoints of a loss L
+ * (g_evals host [nev] and g_evecs device column-major n x nev, either may be
+ * NULL), writes for every stored entry p = (i, j) of the caller's A, in the
+ * caller's CSR order,
+ *   g_vals[p] = S_ij,  S = sum_k g_evals[k] v_k v_k^T - sum_k sym(x_k v_k^T),
+ *   x_k = sum_{j != k} v_j (v_j^T g_k)/(lambda_j - lambda_k)
+ *         + (A - lambda_k I)^-1 on the complement of the evecs applied to
+ *           (I - V V^T) g_k,
+ * so that dL = sum_ij S_ij dA_ij for every symmetric perturbation dA (for an
+ * edge weight w_ij of a Laplacian, dL/dw_ij = S_ii + S_jj - S_ij - S_ji).
+ * The complement solves are CG with A - lambda_k I projected onto the
+ * complement of V, stopped at relative residual tol.  g_vals: device
+ * float64 [nnz].  Errors: MMD_EINVAL (nev out of range, a repeated eigenvalue
+ * whose eigenvector adjoint couples the copies: the gradient is undefined),
+ * MMD_ENOTSPD (the shifted operator is not positive on the complement: the
+ * pairs are not the leftmost ones), MMD_ENOCONV, MMD_EHIP. */
+int eig_backward(mmd_handle* h, int32_t nev, const double* evals, const double* evecs,
+                 const double* g_evals, const double* g_evecs, double tol, double* g_vals,
+                 void* hip_stream);
 /* Apply one level operator to a block of b columns (device, row-major with
  * leading dimension b).  op: 0 = A^(k) (N^(k) -> N^(k)), 1 = M^(k),
  * 2 = B^(k+1) = U^T A^(k) U (reduced -> reduced, needs k < K),

@@ -103,11 +103,12 @@ def lib():
     L.mmd_apply.argtypes = [vp, i32, i32, vp, vp, i32, vp]
     L.mmd_solve.argtypes = [vp, i32, i32, vp, vp, i32, i32, dbl, vp, vp]
     L.mmdk_spmm.argtypes = [i64, i64, vp, vp, vp, vp, vp, i32, vp]
+    L.eig_backward.argtypes = [vp, i32, vp, vp, vp, vp, dbl, vp, vp]
     L.mmd_free.argtypes = [vp]
     L.mmd_free.restype = None
     L.mmd_last_error.restype = ctypes.c_char_p
     for f in ("mmd_build", "mmd_info", "mmd_export", "eig_leftmost", "mmd_apply", "mmd_solve",
-              "mmdk_spmm"):
+              "mmdk_spmm", "eig_backward"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L

@@ -69,6 +69,7 @@ class Decomposition:
         self.h = h
         self._L = lib()
         self.n = n
+        self.nnz = int(rowptr[-1])
 
     @classmethod
     def from_problem(cls, p, **opts):
@@ -146,6 +147,77 @@ class Decomposition:
         check(lib().eig_leftmost(self.h, nev, tol, ctypes.byref(o), _lib._ptr(evals),
                                  _lib._ptr(evecs), ctypes.byref(st), _lib._stream(stream)))
         return evals, evecs, st.as_dict()
+
+
+    def eig_backward(self, evals, evecs, g_evals=None, g_evecs=None, tol=1e-10, stream=None):
+        """Gradient per stored entry of A (CUDA float64 [nnz], the CSR order given
+        to the constructor) of a loss with adjoints g_evals ([nev], host or
+        device) and g_evecs ([nev, n] CUDA, row k = adjoint of eigenvector k)."""
+        import torch
+        evals = np.ascontiguousarray(np.asarray(
+            evals.detach().cpu() if hasattr(evals, "detach") else evals, dtype=np.float64))
+        nev = evals.size
+        evecs = evecs.detach().contiguous()
+        gl = None
+        if g_evals is not None:
+            gl = np.ascontiguousarray(np.asarray(
+                g_evals.detach().cpu() if hasattr(g_evals, "detach") else g_evals,
+                dtype=np.float64))
+        gv = None if g_evecs is None else g_evecs.detach().to(torch.float64).contiguous()
+        out = torch.empty(self.nnz, dtype=torch.float64, device=evecs.device)
+        check(lib().eig_backward(self.h, nev, _lib._ptr(evals), _lib._ptr(evecs),
+                                 None if gl is None else _lib._ptr(gl),
+                                 None if gv is None else _lib._ptr(gv), tol, _lib._ptr(out),
+                                 _lib._stream(stream)))
+        return out
+
+
+class EigLeftmost:
+    """torch.autograd.Function over the stored values of a symmetric CSR matrix.
+
+    ``evals, evecs = EigLeftmost.apply(values, rowptr, col, nev, tol, build)``
+    builds the decomposition of A(values) (``build``: dict of
+    Decomposition options, optionally ``coords`` / ``grid``), returns the nev
+    smallest eigenvalues (CUDA float64 [nev]) and eigenvectors ([nev, n]), and
+    in the backward pass returns dL/dvalues from eig_backward: the gradient for
+    symmetric perturbations, so values built symmetrically from parameters (for
+    example edge weights scattered into a Laplacian) receive the exact chain rule.
+    """
+
+    @staticmethod
+    def _function():
+        import torch
+
+        class _F(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, values, rowptr, col, nev, tol, build):
+                b = dict(build or {})
+                coords, grid = b.pop("coords", None), b.pop("grid", None)
+                dec = Decomposition(np.asarray(rowptr), np.asarray(col),
+                                    values.detach().cpu().numpy(), coords=coords, grid=grid,
+                                    **b)
+                lam, V, _ = dec.eig_leftmost(nev, tol=tol)
+                lam_t = torch.from_numpy(lam).to(V.device)
+                ctx.dec, ctx.tol = dec, tol
+                ctx.save_for_backward(lam_t, V)
+                ctx.dev = values.device
+                return lam_t, V
+
+            @staticmethod
+            def backward(ctx, g_lam, g_V):
+                lam_t, V = ctx.saved_tensors
+                g = ctx.dec.eig_backward(lam_t.cpu().numpy(), V,
+                                         None if g_lam is None else g_lam.detach().cpu().numpy(),
+                                         g_V, tol=ctx.tol)
+                return g.to(ctx.dev), None, None, None, None, None
+
+        return _F
+
+    @classmethod
+    def apply(cls, values, rowptr, col, nev, tol=1e-10, build=None):
+        if not hasattr(cls, "_F"):
+            cls._F = cls._function()
+        return cls._F.apply(values, rowptr, col, nev, tol, build)
 
 
 def spmm(rowptr, col, val, X, n_cols=None, stream=None):

@@ -129,6 +129,16 @@ int eig_leftmost(mmd_handle* h, int32_t nev, double tol, const eig_opts* opts, d
   });
 }
 
+int eig_backward(mmd_handle* h, int32_t nev, const double* evals, const double* evecs,
+                 const double* g_evals, const double* g_evecs, double tol, double* g_vals,
+                 void* hip_stream) {
+  return guarded([&] {
+    MMD_REQUIRE(h && evals && evecs && g_vals, MMD_EINVAL, "null argument");
+    mmd::Solver sv(*h, static_cast<hipStream_t>(hip_stream), default_opts(nullptr), nullptr);
+    sv.backward(nev, evals, evecs, g_evals, g_evecs, tol, g_vals);
+  });
+}
+
 int mmd_apply(mmd_handle* h, int32_t level, int32_t op, const double* X, double* Y, int32_t b,
               void* hip_stream) {
   return guarded([&] {

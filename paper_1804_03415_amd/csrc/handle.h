@@ -59,6 +59,10 @@ struct mmd_handle {
   std::vector<int> perm;
   mmd::DBuf<int> d_perm;
   mmd::HostCSR A_user;  // the caller's matrix in its own numbering (export)
+  // the caller's CSR pattern on the device (eigen-backward output order), made
+  // on first use
+  mmd::DBuf<int> u_ptr, u_col;
+  bool has_upat = false;
   std::vector<mmd::LevelHost> host;
   std::vector<mmd::LevelDev> dev;
   std::vector<double> eps;  // cumulative eps_k, eps[0] = 0

@@ -133,6 +133,17 @@ void col_absmax(const double* X, int ldx, int n, int b, int* idx, double* val,
 void permute_rows(const double* X, int ldx, double* Y, int ldy, int n, int b, const int* idx,
                   bool scatter, hipStream_t s);
 
+// row-major out[i*ld + c] = in[c*n + (perm ? perm[i] : i)]  (column-major caller
+// block to the internal row-major numbering)
+void from_colmajor(const double* in, int n, int b, const int* perm, double* out, int ld,
+                   hipStream_t s);
+// Eigen-backward sampled product on a CSR pattern (rows of V, X row-major with
+// leading dimension ld, nev columns): for every stored (i, j)
+//   out[p] = sum_k glam[k] V(i,k) V(j,k) - (X(i,k) V(j,k) + V(i,k) X(j,k)) / 2
+// glam may be null (no eigenvalue term), X may be null (no vector term).
+void sddmm_eig(int n_rows, const int* rowptr, const int* col, const double* V, const double* X,
+               int ld, int nev, const double* glam, double* out, hipStream_t s);
+
 // int64 -> int32 copy of caller row pointers (the caller checks nnz < 2^31)
 void i64_to_i32(const int64_t* src, int* dst, int64_t n, hipStream_t s);
 

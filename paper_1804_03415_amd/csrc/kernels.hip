@@ -698,6 +698,45 @@ __global__ void k_to_colmajor(const double* __restrict__ X, int ldx,
   out[c * n + o] = X[i * ldx + c] * scale[c];
 }
 
+__global__ void k_from_colmajor(const double* __restrict__ in, int n, int b,
+                                const int* __restrict__ perm, double* __restrict__ out, int ld) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * b) return;
+  const int64_t i = t / b, c = t % b;
+  const int64_t src = perm ? perm[i] : i;
+  out[i * ld + c] = in[c * n + src];
+}
+
+// One wavefront per row, lanes over the row's nonzeros; the row's own factor
+// entries are the same address for every lane (one broadcast load each).
+__global__ __launch_bounds__(kBlock) void k_sddmm_eig(int n_rows, const int* __restrict__ rowptr,
+                                                      const int* __restrict__ col,
+                                                      const double* __restrict__ V,
+                                                      const double* __restrict__ X, int ld,
+                                                      int nev, const double* __restrict__ glam,
+                                                      double* __restrict__ out) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int row = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  if (row >= n_rows) return;
+  const int lo = rowptr[row], hi = rowptr[row + 1];
+  const double* vi = V + (size_t)row * ld;
+  const double* xi = X ? X + (size_t)row * ld : nullptr;
+  for (int p = lo + lane; p < hi; p += kWave) {
+    const int j = col[p];
+    const double* vj = V + (size_t)j * ld;
+    double acc = 0.0;
+    if (glam)
+      for (int k = 0; k < nev; ++k) acc += glam[k] * vi[k] * vj[k];
+    if (X) {
+      const double* xj = X + (size_t)j * ld;
+      double t = 0.0;
+      for (int k = 0; k < nev; ++k) t += xi[k] * vj[k] + vi[k] * xj[k];
+      acc -= 0.5 * t;
+    }
+    out[p] = acc;
+  }
+}
+
 __global__ void k_permute_rows(const double* __restrict__ X, int ldx, double* __restrict__ Y,
                                int ldy, int n, int b, const int* __restrict__ idx, int scatter) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1077,6 +1116,22 @@ void gather_scalars(ColScalars src, ColScalars dst, const int* idx, int m, hipSt
   if (m == 0) return;
   hipLaunchKernelGGL(k_gather_scalars, dim3(ceil_div(m, kBlock)), dim3(kBlock), 0, s, src, dst,
                      idx, m);
+  check_launch();
+}
+
+void from_colmajor(const double* in, int n, int b, const int* perm, double* out, int ld,
+                   hipStream_t s) {
+  if ((int64_t)n * b == 0) return;
+  hipLaunchKernelGGL(k_from_colmajor, dim3(ew_grid((int64_t)n * b)), dim3(kBlock), 0, s, in, n, b,
+                     perm, out, ld);
+  check_launch();
+}
+
+void sddmm_eig(int n_rows, const int* rowptr, const int* col, const double* V, const double* X,
+               int ld, int nev, const double* glam, double* out, hipStream_t s) {
+  if (n_rows == 0) return;
+  hipLaunchKernelGGL(k_sddmm_eig, dim3(ceil_div(n_rows, kBlock / kWave)), dim3(kBlock), 0, s,
+                     n_rows, rowptr, col, V, X, ld, nev, glam, out);
   check_launch();
 }
 

@@ -62,19 +62,6 @@ void uniform_vector(std::vector<double>& v, int n, uint64_t seed, int level, int
   for (int j = 0; j < n; ++j) v[j] = perm ? u[(*perm)[j]] : u[j];
 }
 
-ColScalars make_scalars(Pool& pool, const std::string& tag, int b) {
-  ColScalars sc;
-  sc.rr = pool.d(tag + ":rr", b);
-  sc.rr2 = pool.d(tag + ":rr2", b);
-  sc.alpha = pool.d(tag + ":al", b);
-  sc.beta = pool.d(tag + ":be", b);
-  sc.bn2 = pool.d(tag + ":bn", b);
-  sc.tol2 = pool.d(tag + ":tol", b);
-  sc.active = pool.i(tag + ":act", b);
-  sc.iters = pool.i(tag + ":it", b);
-  sc.notspd = pool.i(tag + ":spd", 1);
-  return sc;
-}
 
 // Tridiagonal part of the dense Lanczos matrix (fill from restarts is rounding).
 void tri_of(const std::vector<double>& T, int ld, int m, std::vector<double>& d,
@@ -124,6 +111,20 @@ struct PhaseTimer {
 };
 
 }  // namespace
+
+ColScalars make_scalars(Pool& pool, const std::string& tag, int b) {
+  ColScalars sc;
+  sc.rr = pool.d(tag + ":rr", b);
+  sc.rr2 = pool.d(tag + ":rr2", b);
+  sc.alpha = pool.d(tag + ":al", b);
+  sc.beta = pool.d(tag + ":be", b);
+  sc.bn2 = pool.d(tag + ":bn", b);
+  sc.tol2 = pool.d(tag + ":tol", b);
+  sc.active = pool.i(tag + ":act", b);
+  sc.iters = pool.i(tag + ":it", b);
+  sc.notspd = pool.i(tag + ":spd", 1);
+  return sc;
+}
 
 struct Solver::Lanczos {
   int k = 0, n = 0;

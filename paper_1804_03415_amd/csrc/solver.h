@@ -23,6 +23,9 @@ class Pool {
   std::map<std::string, DBuf<float>> flt_;
 };
 
+// Per-column CG scalars backed by named pool buffers of length b.
+ColScalars make_scalars(Pool& pool, const std::string& tag, int b);
+
 struct SolveResult {
   std::vector<int> iters;
 };
@@ -39,6 +42,9 @@ class Solver {
   void apply_op(int level, int op, const double* X, double* Y, int b);
   void solve(int level, int kind, const double* rhs, double* X, int b, bool use_x0, double tol,
              int* iters_out);
+  // eig_backward: gradient per stored entry of the caller's A (device g_vals)
+  void backward(int nev, const double* evals, const double* evecs, const double* g_evals,
+                const double* g_evecs, double tol, double* g_vals);
 
  private:
   struct Block {  // row-major device block n x b (ld = b)
@@ -76,6 +82,10 @@ class Solver {
   void cg32(float* R32, int m, const std::vector<int>& gcols, double* X, int ldx, double eta,
             std::vector<int>& its);
   void ensure32();
+  // CG on P (A - diag shift) P, P = I - V V^T, for the columns of R (row-major
+  // n x b, in V-perp); Y receives the solutions (zero start)
+  void cg_shift_defl(const double* R, double* Y, int b, const double* shift_neg,
+                     const double* V, int nev, double tol);
 
   // Lanczos / extension / refinement
   struct Lanczos;
