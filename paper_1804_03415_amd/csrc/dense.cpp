@@ -206,17 +206,24 @@ void sym_eig(int n, const double* a_in, std::vector<double>& w, std::vector<doub
 }
 
 bool cholesky_upper(int n, const double* g, std::vector<double>& r) {
+  // right-looking, row-major: after step j, row j holds R(j, j..n-1) and the
+  // trailing rows hold the Schur complement (contiguous row updates)
   r.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int k = i; k < n; ++k) r[(size_t)i * n + k] = 0.5 * (g[(size_t)i * n + k] + g[(size_t)k * n + i]);
   for (int j = 0; j < n; ++j) {
-    double s = g[(size_t)j * n + j];
-    for (int k = 0; k < j; ++k) s -= r[(size_t)k * n + j] * r[(size_t)k * n + j];
-    if (!(s > 0.0)) return false;
-    const double rjj = std::sqrt(s);
-    r[(size_t)j * n + j] = rjj;
+    double* rj = r.data() + (size_t)j * n;
+    const double d = rj[j];
+    if (!(d > 0.0)) return false;
+    const double rjj = std::sqrt(d);
+    const double inv = 1.0 / rjj;
+    rj[j] = rjj;
+    for (int k = j + 1; k < n; ++k) rj[k] *= inv;
     for (int i = j + 1; i < n; ++i) {
-      double t = 0.5 * (g[(size_t)j * n + i] + g[(size_t)i * n + j]);
-      for (int k = 0; k < j; ++k) t -= r[(size_t)k * n + j] * r[(size_t)k * n + i];
-      r[(size_t)j * n + i] = t / rjj;
+      const double f = rj[i];
+      if (f == 0.0) continue;
+      double* ri = r.data() + (size_t)i * n;
+      for (int k = i; k < n; ++k) ri[k] -= f * rj[k];
     }
   }
   return true;

@@ -4,6 +4,9 @@
 // Galerkin level operators A^(k), M^(k), and their upload to the device.
 #include <omp.h>
 
+#include <cstdio>
+#include <cstdlib>
+
 #include <algorithm>
 #include <cmath>
 #include <limits>
@@ -331,17 +334,29 @@ void dense_sub(const HostCSR& A, const std::vector<int>& S, std::vector<double>&
 
 // solve (R^T R) X = B in place for nrhs columns of the row-major m x nrhs B
 void chol_solve(int m, const std::vector<double>& R, double* B, int nrhs) {
-  for (int c = 0; c < nrhs; ++c) {
-    for (int i = 0; i < m; ++i) {  // R^T y = b
-      double s = B[(size_t)i * nrhs + c];
-      for (int k = 0; k < i; ++k) s -= R[(size_t)k * m + i] * B[(size_t)k * nrhs + c];
-      B[(size_t)i * nrhs + c] = s / R[(size_t)i * m + i];
+  // R^T y = b, then R x = y, for all right-hand sides at once (rows of B are
+  // contiguous over the right-hand sides)
+  for (int i = 0; i < m; ++i) {
+    double* bi = B + (size_t)i * nrhs;
+    const double inv = 1.0 / R[(size_t)i * m + i];
+    for (int c = 0; c < nrhs; ++c) bi[c] *= inv;
+    for (int k = i + 1; k < m; ++k) {
+      const double f = R[(size_t)i * m + k];
+      if (f == 0.0) continue;
+      double* bk = B + (size_t)k * nrhs;
+      for (int c = 0; c < nrhs; ++c) bk[c] -= f * bi[c];
     }
-    for (int i = m - 1; i >= 0; --i) {  // R x = y
-      double s = B[(size_t)i * nrhs + c];
-      for (int k = i + 1; k < m; ++k) s -= R[(size_t)i * m + k] * B[(size_t)k * nrhs + c];
-      B[(size_t)i * nrhs + c] = s / R[(size_t)i * m + i];
+  }
+  for (int i = m - 1; i >= 0; --i) {
+    double* bi = B + (size_t)i * nrhs;
+    for (int k = i + 1; k < m; ++k) {
+      const double f = R[(size_t)i * m + k];
+      if (f == 0.0) continue;
+      const double* bk = B + (size_t)k * nrhs;
+      for (int c = 0; c < nrhs; ++c) bi[c] -= f * bk[c];
     }
+    const double inv = 1.0 / R[(size_t)i * m + i];
+    for (int c = 0; c < nrhs; ++c) bi[c] *= inv;
   }
 }
 
@@ -456,13 +471,16 @@ HostCSR psi_localized(const HostCSR& A, const Patches& P, const std::vector<doub
     }
     std::vector<double> PhiC = Y;
     chol_solve(ms, R, Y.data(), mc);
-    std::vector<double> G((size_t)mc * mc, 0.0);
-    for (int a = 0; a < mc; ++a)
-      for (int b = 0; b < mc; ++b) {
-        double s = 0.0;
-        for (int i = 0; i < ms; ++i) s += PhiC[(size_t)i * mc + a] * Y[(size_t)i * mc + b];
-        G[(size_t)a * mc + b] = s;
+    std::vector<double> G((size_t)mc * mc, 0.0);  // G = PhiC^T Y, row updates
+    for (int i = 0; i < ms; ++i) {
+      const double* yi = Y.data() + (size_t)i * mc;
+      for (int a = 0; a < mc; ++a) {
+        const double f = PhiC[(size_t)i * mc + a];
+        if (f == 0.0) continue;
+        double* ga = G.data() + (size_t)a * mc;
+        for (int b = 0; b < mc; ++b) ga[b] += f * yi[b];
       }
+    }
     for (int a = 0; a < mc; ++a)
       for (int b = a + 1; b < mc; ++b) {
         const double v = 0.5 * (G[(size_t)a * mc + b] + G[(size_t)b * mc + a]);
@@ -590,6 +608,7 @@ void build_hierarchy(mmd_handle& h, const mmd_csr& in, const mmd_build_opts& o) 
   h.A_user = HostCSR();
 
   for (int k = 1; k <= levels; ++k) {
+    const double t_level = omp_get_wtime();
     const LevelHost& prev = h.host[k - 1];
     const HostCSR& Ak = prev.A;
     Patches P;
@@ -671,6 +690,11 @@ void build_hierarchy(mmd_handle& h, const mmd_csr& in, const mmd_build_opts& o) 
       }
     }
     L.grid = cgrid;
+    if (const char* e = std::getenv("MMDEIG_LOG"))
+      if (std::atoi(e) != 0)
+        std::fprintf(stderr, "[mmd_build] level %d: %d -> %d dofs, nnz(A) %lld, eps %.4g, %.2f s\n",
+                     k, prev.n, np, static_cast<long long>(L.A.nnz()), L.eps_level,
+                     omp_get_wtime() - t_level);
     h.host.push_back(std::move(L));
     h.eps.push_back(h.eps.back() + h.host.back().eps_level);
   }
