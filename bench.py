@@ -76,14 +76,18 @@ def cluster_angles(lam, V, W, gap=1e-6):
 
 def timed_solves(dec, a, precision, steps, warmup):
     import torch
-    for _ in range(warmup):
-        dec.eig_leftmost(a.nev, tol=a.tol, precision=precision)
+    for w in range(warmup):
+        _, _, st = dec.eig_leftmost(a.nev, tol=a.tol, precision=precision)
+        print("%s warmup %d: %.2f s" % (precision, w, st["seconds_total"]), file=sys.stderr,
+              flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = []
-    for _ in range(steps):
+    for s_ in range(steps):
         lam, V, st = dec.eig_leftmost(a.nev, tol=a.tol, precision=precision)
         stats.append(st)
+        print("%s step %d: %.2f s" % (precision, s_, st["seconds_total"]), file=sys.stderr,
+              flush=True)
     torch.cuda.synchronize()
     return lam, V, stats, time.perf_counter() - t0
 

@@ -556,11 +556,15 @@ def eig_leftmost(A, nev, tol, mmd: Optional[MMD] = None, alpha=3.0, beta=1.0, c=
         V, D = coarsest(mmd, sch.mu_ex[K], nev)
         stats.lev(K)["ext_out"] = V.shape[1]
     for k in range(K - 1, -1, -1):
-        ops = LevelOps(mmd, k, sch.eps_op[k], stats, E0)
+        # the PCG of OP and of the refinement stops at a relative residual
+        # eps^(k); without the paper's scaling (lambda_1 = 1) eps^(k) = 0.1 eps_k
+        # can exceed 1, where x = 0 already passes and OP vanishes: the
+        # relative tolerance on levels k >= 1 is min(eps^(k), 0.1)
+        t_pcg = 0.1 * sch.eps_op[k] if k == 0 else min(0.1, sch.eps_op[k])
+        ops = LevelOps(mmd, k, sch.eps_op[k] if k == 0 else t_pcg, stats, E0)
         V = mmd.levels[k + 1].Psi @ V
         V, D = refine(ops, V, D, sch.eps_op[k], sch.mu_re[k], mmd.levels[k].lam_max_M,
-                      gamma=(1.0 + beta) / alpha,
-                      eps_solve=0.1 * sch.eps_op[k] if k == 0 else sch.eps_op[k])
+                      gamma=(1.0 + beta) / alpha, eps_solve=t_pcg)
         V, D = extend(ops, V, D, nev, sch.eps_op[k], sch.mu_ex[k], sch.d[k], c,
                       relative=(k == 0), seed=seed)
     if K == 0:

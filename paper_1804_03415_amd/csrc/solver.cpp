@@ -915,7 +915,7 @@ void Solver::extend(int k, double*& V, std::vector<double>& D, int& m, int m_tar
   const int c = o_.restart_mult;
   const int vcap = std::min(cap, want + c * std::max(want, d));
   Lanczos L;
-  L.eps_op = eps;
+  L.eps_op = k == 0 ? eps : tpcg_[k];
   lanczos_init(L, k, V, mi, vcap);
   int kcur = 0, restarts = 0;
   auto converge = [&](int kk, int p) {
@@ -1074,8 +1074,9 @@ void Solver::refine(int k, double*& V, std::vector<double>& D, int& m, double ep
   double* Pd = pool_.d("rf:P", (size_t)ml * ml);
   double* Sd = pool_.d("rf:S", (size_t)ml * ml);
   double* work = pool_.d("gram:w", gram_work_size(n, ml, ml));
-  // on level 0 the solves run at 0.1 eps so the stop test lies above their noise
-  const double eps_solve = k == 0 ? 0.1 * eps : eps;
+  // on level 0 the solves run at 0.1 eps so the stop test lies above their noise;
+  // coarse levels use the relative PCG tolerance of the level
+  const double eps_solve = k == 0 ? 0.1 * eps : tpcg_[k];
   // start block F = Q D + U G, g_i = cg(B, U^T M q_i, 0, eps)
   applyM(k, V, ml, MQ, ml, ml);
   if (nred > 0) {
@@ -1250,6 +1251,11 @@ void Solver::leftmost(int nev, double tol, double* evals, double* evecs) {
   const double alpha = o_.alpha, beta = o_.beta, gamma = (1.0 + beta) / alpha;
   std::vector<double> eps_op(K + 1), mu_re(K + 1), mu_ex(K + 1);
   std::vector<int> dd(K + 1);
+  // PCG solves stop at the relative residual eps^(k); without the paper's
+  // scaling (lambda_1 = 1) eps^(k) = 0.1 eps_k can exceed 1, where x = 0
+  // already passes and OP vanishes: levels k >= 1 use min(eps^(k), 0.1)
+  tpcg_.assign(K + 1, tol);
+  for (int k = 1; k <= K; ++k) tpcg_[k] = std::min(0.1, 0.1 * h_.eps[k]);
   for (int k = 0; k <= K; ++k) {
     eps_op[k] = k == 0 ? tol : 0.1 * h_.eps[k];
     mu_re[k] = k + 1 <= K ? alpha * h_.eps[k + 1] : 0.0;

@@ -137,6 +137,7 @@ class Solver {
   bool use_persistent_ = true;
   std::map<int, Pcg1Plan> plans_;  // resident plain-CG plan per level (level 0)
   double norm_a0_ = 0.0;           // ||A||_inf of level 0 (mixed-precision floor test)
+  std::vector<double> tpcg_;       // relative PCG tolerance per level (k >= 1)
   int cur_level_ = 0;
   int64_t draws_[MMD_MAX_LEVELS] = {};
 };
