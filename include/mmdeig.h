@@ -83,6 +83,9 @@ typedef struct {
   uint64_t seed;           /* Philox key of the random start vectors [0]         */
   int32_t max_restarts;    /* per extension [2000]                               */
   int32_t max_refine;      /* refinement iterations per level [200]              */
+  int32_t streams;         /* eig_leftmost_batched: problems solved concurrently,
+                              one HIP stream and host thread each [8]           */
+  int32_t reserved;
 } eig_opts;
 
 #define MMD_MAX_LEVELS 16
@@ -158,6 +161,18 @@ int mmd_export(const mmd_handle* h, int32_t level, int32_t which, int64_t* n_row
 int eig_leftmost(mmd_handle* h, int32_t nev, double tol, const eig_opts* opts,
                  double* evals, double* evecs, eig_stats* st, void* hip_stream);
 
+/* Many independent problems at once: the same computation as eig_leftmost
+ * for hs[b], nev[b], evals[b], evecs[b], b < B (distinct handles), with
+ * opts->streams problems in flight at a time, each on its own HIP stream
+ * driven by its own host thread, largest nnz x nev first.  Work on the
+ * caller's stream that precedes the call is waited for; the results are
+ * complete when the call returns.  Within a batch the single-vector solves
+ * use block kernels rather than the cooperative persistent ones, which need
+ * the whole device.  st: NULL or an array of B counters.  The first error of
+ * any problem is returned (the others are still finished). */
+int eig_leftmost_batched(int32_t B, mmd_handle* const* hs, const int32_t* nev, double tol,
+                         const eig_opts* opts, double* const* evals, double* const* evecs,
+                         eig_stats* st, void* hip_stream);
 /* Reverse-mode derivative of the nev leftmost eigenpairs (the paper gives
  * none; first-order perturbation of a symmetric matrix).  Given the pairs
  * returned by eig_leftmost (evals host [nev] ascending, evecs device

@@ -4,7 +4,8 @@ The compute path is the C-ABI library libmmdeig.so (include/mmdeig.h); this
 package only marshals arguments to it.
 """
 from ._lib import MMDError, lib  # noqa: F401
-from .api import Decomposition, EigLeftmost, build_options, solver_options, spmm  # noqa: F401
+from .api import (Decomposition, EigLeftmost, build_options, eig_leftmost_batched,  # noqa: F401
+                  solver_options, spmm)
 
-__all__ = ["Decomposition", "EigLeftmost", "MMDError", "build_options", "solver_options",
-           "spmm", "lib"]
+__all__ = ["Decomposition", "EigLeftmost", "MMDError", "build_options", "eig_leftmost_batched",
+           "solver_options", "spmm", "lib"]

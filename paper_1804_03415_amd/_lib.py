@@ -43,7 +43,8 @@ class eig_opts(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double),
                 ("restart_mult", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("max_restarts", ctypes.c_int32),
-                ("max_refine", ctypes.c_int32)]
+                ("max_refine", ctypes.c_int32),
+                ("streams", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _L = MMD_MAX_LEVELS
@@ -104,11 +105,13 @@ def lib():
     L.mmd_solve.argtypes = [vp, i32, i32, vp, vp, i32, i32, dbl, vp, vp]
     L.mmdk_spmm.argtypes = [i64, i64, vp, vp, vp, vp, vp, i32, vp]
     L.eig_backward.argtypes = [vp, i32, vp, vp, vp, vp, dbl, vp, vp]
+    L.eig_leftmost_batched.argtypes = [i32, vp, vp, dbl, ctypes.POINTER(eig_opts), vp, vp, vp,
+                                       vp]
     L.mmd_free.argtypes = [vp]
     L.mmd_free.restype = None
     L.mmd_last_error.restype = ctypes.c_char_p
     for f in ("mmd_build", "mmd_info", "mmd_export", "eig_leftmost", "mmd_apply", "mmd_solve",
-              "mmdk_spmm", "eig_backward"):
+              "mmdk_spmm", "eig_backward", "eig_leftmost_batched"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L

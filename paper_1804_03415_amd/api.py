@@ -30,7 +30,7 @@ def build_options(levels=3, targets=(4, 8), grid_blocks=(4, 2), r_hops=1, exact_
 
 
 def solver_options(alpha=3.0, beta=1.0, restart_mult=1, seed=0, max_restarts=2000,
-                   max_refine=200, precision="fp64"):
+                   max_refine=200, precision="fp64", streams=8):
     """eig_opts; precision "fp64" or "fp32-refine" (FP32 CG inside FP64
     iterative refinement for the level-0 block solves)."""
     o = eig_opts()
@@ -39,6 +39,7 @@ def solver_options(alpha=3.0, beta=1.0, restart_mult=1, seed=0, max_restarts=200
     if precision not in ("fp64", "fp32-refine"):
         raise ValueError("precision must be 'fp64' or 'fp32-refine'")
     o.precision = 0 if precision == "fp64" else 1
+    o.streams = streams
     return o
 
 
@@ -170,6 +171,27 @@ class Decomposition:
                                  None if gv is None else _lib._ptr(gv), tol, _lib._ptr(out),
                                  _lib._stream(stream)))
         return out
+
+
+def eig_leftmost_batched(decs, nevs, tol=1e-10, stream=None, **opts):
+    """eig_leftmost for many decompositions at once (opts["streams"] in flight).
+    Returns a list of (evals, evecs, stats) in the order of decs."""
+    import torch
+    B = len(decs)
+    nev = np.ascontiguousarray(nevs, dtype=np.int32)
+    if nev.shape != (B,):
+        raise ValueError("one nev per decomposition")
+    evals = [np.zeros(int(k)) for k in nev]
+    evecs = [torch.empty((int(k), d.n), dtype=torch.float64, device="cuda")
+             for k, d in zip(nev, decs)]
+    hs = (ctypes.c_void_p * B)(*[d.h.value for d in decs])
+    ev_p = (ctypes.c_void_p * B)(*[_lib._ptr(e) for e in evals])
+    vec_p = (ctypes.c_void_p * B)(*[_lib._ptr(v) for v in evecs])
+    st = (eig_stats * B)()
+    o = solver_options(**opts)
+    check(lib().eig_leftmost_batched(B, hs, _lib._ptr(nev), tol, ctypes.byref(o), ev_p, vec_p,
+                                     st, _lib._stream(stream)))
+    return [(evals[b], evecs[b], st[b].as_dict()) for b in range(B)]
 
 
 class EigLeftmost:

@@ -3,6 +3,7 @@
 #include <cstring>
 #include <string>
 
+#include "batch.h"
 #include "handle.h"
 #include "solver.h"
 
@@ -126,6 +127,15 @@ int eig_leftmost(mmd_handle* h, int32_t nev, double tol, const eig_opts* opts, d
     MMD_REQUIRE(h && evals && evecs, MMD_EINVAL, "null argument");
     mmd::Solver sv(*h, static_cast<hipStream_t>(hip_stream), default_opts(opts), st);
     sv.leftmost(nev, tol, evals, evecs);
+  });
+}
+
+int eig_leftmost_batched(int32_t B, mmd_handle* const* hs, const int32_t* nev, double tol,
+                         const eig_opts* opts, double* const* evals, double* const* evecs,
+                         eig_stats* st, void* hip_stream) {
+  return guarded([&] {
+    mmd::leftmost_batched(B, hs, nev, tol, default_opts(opts), evals, evecs, st,
+                          static_cast<hipStream_t>(hip_stream));
   });
 }
 

@@ -505,20 +505,20 @@ int lanes_for(double avg) {
 }  // namespace
 
 int pcg1_grid() {
-  static int cached = 0;
-  if (cached) return cached;
-  (void)0;
-  int dev = 0;
-  MMD_HIP(hipGetDevice(&dev));
-  int coop = 0;
-  MMD_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
-  MMD_REQUIRE(coop != 0, MMD_EHIP, "device does not support cooperative launches");
-  int cus = 0;
-  MMD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  int per = 0;
-  MMD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_pcg1, kThreads, 0));
-  MMD_REQUIRE(per > 0, MMD_EHIP, "persistent PCG kernel cannot be resident");
-  cached = cus * per;  // upper bound for co-residency
+  // computed once per process (thread-safe initialisation)
+  static const int cached = [] {
+    int dev = 0;
+    MMD_HIP(hipGetDevice(&dev));
+    int coop = 0;
+    MMD_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    MMD_REQUIRE(coop != 0, MMD_EHIP, "device does not support cooperative launches");
+    int cus = 0;
+    MMD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    int per = 0;
+    MMD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_pcg1, kThreads, 0));
+    MMD_REQUIRE(per > 0, MMD_EHIP, "persistent PCG kernel cannot be resident");
+    return cus * per;  // upper bound for co-residency
+  }();
   return cached;
 }
 

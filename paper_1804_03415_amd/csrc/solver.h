@@ -37,6 +37,10 @@ class Solver {
 
   // eig_leftmost: evals ascending (host), evecs column-major n x nev (device)
   void leftmost(int nev, double tol, double* evals, double* evecs);
+  // off: single-vector solves use the block kernels instead of the
+  // cooperative persistent ones (needed when other streams run concurrently:
+  // a grid barrier must never wait on workgroups that cannot be resident)
+  void set_persistent(bool on) { use_persistent_ = on; }
 
   // building blocks exposed through mmd_apply / mmd_solve
   void apply_op(int level, int op, const double* X, double* Y, int b);

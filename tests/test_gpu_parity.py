@@ -254,3 +254,23 @@ def test_eig_mixed(torch_cuda, case):
     assert np.max(np.abs(lam - l64) / l64) < 1e-10
     a64, _ = dense.cluster_angles(l64, V64.cpu().numpy().T, V)
     assert a64[full].max() < 1e-8
+
+
+def test_eig_knn_coarse_tolerance(torch_cuda):
+    """kNN graph whose coarse-level eps^(k) = 0.1 eps_k exceeds 1 (no rescaling):
+    the capped relative PCG tolerance keeps OP nonzero on those levels; GPU and
+    oracle agree with dense eigenpairs."""
+    p = wl.knn_gmm(3000, 10, 1)
+    kw = dict(levels=3, exact_max_n=8000)
+    lam, V, st, lo, Vo = _run_both(p, 12, 1e-10, kw)
+    A = p.scipy()
+    w, Z = dense.smallest_dense(A, 12)
+    # the null eigenvalue 1e-6 is known to absolute u ||A|| only
+    null = np.abs(w - 1e-6) < 1e-12
+    assert np.sum(np.abs(lo - 1e-6) < 1e-12) == np.sum(null)
+    assert np.sum(np.abs(lam - 1e-6) < 1e-12) == np.sum(null)
+    assert np.max(np.abs(lo[~null] - w[~null]) / w[~null]) < 1e-10
+    assert np.max(np.abs(lam[~null] - w[~null]) / w[~null]) < 1e-10
+    ang, cl = dense.cluster_angles(w, Z, V)
+    assert ang.max() < 1e-8
+    assert dense.rel_residuals(A, lam, V).max() < 1e-8
