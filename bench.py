@@ -49,10 +49,15 @@ def parse():
     ap.add_argument("--traffic-bytes", type=float, default=None,
                     help="HBM bytes per launch of the dominant kernel from rocprofv3 counters")
     ap.add_argument("--verbose", type=int, default=0)
-    ap.add_argument("--workload", default="rgg", choices=["rgg", "knn-backward"],
+    ap.add_argument("--workload", default="rgg", choices=["rgg", "knn-backward", "rgg-batch"],
                     help="rgg: the leftmost-300 eigensolve of the n = 1e5 RGG (default); "
                          "knn-backward: forward (20 pairs) and eigen-backward of the "
-                         "n = 2e5 kNN-GMM graph")
+                         "n = 2e5 kNN-GMM graph; rgg-batch: 100 pairs of each of a batch "
+                         "of RGGs with sizes uniform in [5000, 50000]")
+    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--streams", type=int, default=8)
+    ap.add_argument("--batch-sequential", type=int, default=1,
+                    help="also time the batch one problem after another (eig_leftmost)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 5 times (the reference kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings) and exit")
@@ -194,6 +199,60 @@ def knn_backward(a):
     print(json.dumps(out), flush=True)
 
 
+def rgg_batch(a):
+    """Throughput of eig_leftmost_batched on a batch of RGG Laplacians (mean
+    degree 8, + 1e-6 I, sizes uniform in [5000, 50000], 100 pairs each),
+    against solving the same problems one after another."""
+    import torch
+    import workloads
+    from paper_1804_03415_amd import Decomposition, eig_leftmost_batched
+    nev = 100
+    probs = workloads.rgg_batch(a.batch_count, seed=0)
+    t = time.perf_counter()
+    decs = [Decomposition.from_problem(q, levels=a.levels, targets=(4, 8)) for q in probs]
+    t_build = time.perf_counter() - t
+    print("rgg-batch: %d problems, sum n %d, build %.1f s" % (
+        len(probs), sum(q.n for q in probs), t_build), file=sys.stderr, flush=True)
+    # warm-up: load every kernel once on a small member
+    small = min(range(len(probs)), key=lambda b: probs[b].n)
+    eig_leftmost_batched([decs[small]], [nev], tol=a.tol, streams=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = eig_leftmost_batched(decs, [nev] * len(decs), tol=a.tol, streams=a.streams)
+    torch.cuda.synchronize()
+    el_b = time.perf_counter() - t0
+    print("rgg-batch: batched %.1f s" % el_b, file=sys.stderr, flush=True)
+    worst = 0.0
+    for q, (lam, V, st) in zip(probs, out):
+        Vh = V.cpu().numpy().T
+        A = q.scipy()
+        rho = np.linalg.norm(A @ Vh - Vh * lam[None, :], axis=0) / (np.abs(lam) * np.linalg.norm(Vh, axis=0))
+        worst = max(worst, float(rho.max()))
+    seq = None
+    if a.batch_sequential:
+        t0 = time.perf_counter()
+        for b, dec in enumerate(decs):
+            dec.eig_leftmost(nev, tol=a.tol)
+            if b % 8 == 7:
+                print("rgg-batch: sequential %d/%d %.1f s" % (b + 1, len(decs),
+                      time.perf_counter() - t0), file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        el_s = time.perf_counter() - t0
+        seq = {"value": round(nev * len(decs) / el_s, 3), "seconds": round(el_s, 2)}
+    res = {"metric": "eigenpairs/s at rel. residual 1e-8 (batch)",
+           "value": round(nev * len(decs) / el_b, 3), "unit": "eigenpairs/s", "n_gpus": 1,
+           "steps": 1, "warmup": 1, "ms_per_step": round(1000.0 * el_b, 2),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "rgg_batch_%d_n5000-50000_nev100" % len(decs),
+                      "sum_n": int(sum(q.n for q in probs)),
+                      "sum_nnz": int(sum(q.nnz for q in probs)), "nev": nev, "tol": a.tol,
+                      "streams": a.streams, "build_s": round(t_build, 2)},
+           "max_rel_residual": worst, "residual_ok": bool(worst <= 1e-8),
+           "sequential": seq}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -216,6 +275,8 @@ def main():
     torch.cuda.set_device(0)
     if a.workload == "knn-backward":
         return knn_backward(a)
+    if a.workload == "rgg-batch":
+        return rgg_batch(a)
     p = workloads.rgg(a.n, 0)
     t = time.perf_counter()
     dec = Decomposition.from_problem(p, levels=a.levels, targets=(4, 8))
