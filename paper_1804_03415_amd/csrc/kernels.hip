@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "common.h"
 #include "kernels.h"
@@ -143,7 +144,7 @@ __device__ inline double readlane_d(double v, int k) {
   return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
 }
 
-template <bool EDGE, bool FUSE>
+template <bool EDGE, bool FUSE, int U, int STEP>
 __global__ __launch_bounds__(kBlock) void k_spmm_r64(
     int n_rows, const int* __restrict__ rowptr, const int* __restrict__ col,
     const double* __restrict__ val, const double* __restrict__ diag,
@@ -165,67 +166,97 @@ __global__ __launch_bounds__(kBlock) void k_spmm_r64(
   const int rpx = (n_rows + nx - 1) / nx;
   const int rhi = min(n_rows, (xcd + 1) * rpx);
   const int stride = bpx * WPB;
-  for (int row0 = xcd * rpx + bl * WPB + wid; row0 < rhi; row0 += 2 * stride) {
-    const int row1 = row0 + stride;
-    const bool ok1 = row1 < rhi;
-    const int r1 = ok1 ? row1 : row0;
-    const int lo0 = rowptr[row0], hi0 = rowptr[row0 + 1];
-    const int lo1 = ok1 ? rowptr[row1] : 0, hi1 = ok1 ? rowptr[row1 + 1] : 0;
-    const double xi0 = EDGE ? X[(size_t)row0 * ldx + cx] : 0.0;
-    const double xi1 = EDGE ? X[(size_t)r1 * ldx + cx] : 0.0;
-    double a0 = 0.0, a1 = 0.0;
-    for (int b0 = lo0, b1 = lo1; b0 < hi0 || b1 < hi1; b0 += kWave, b1 += kWave) {
-      const int n0 = max(0, min(kWave, hi0 - b0)), n1 = max(0, min(kWave, hi1 - b1));
-      const int jv0 = lane < n0 ? col[b0 + lane] : 0;
-      const double vv0 = lane < n0 ? val[b0 + lane] : 0.0;
-      const int jv1 = lane < n1 ? col[b1 + lane] : 0;
-      const double vv1 = lane < n1 ? val[b1 + lane] : 0.0;
-      // steps of kStep slots with a fixed trip count, so all 2 * kStep gathers
-      // of a step are in flight together (padding slots carry weight 0)
-      const int m = max(n0, n1);
-      for (int k0 = 0; k0 < m; k0 += kStep) {
-        double x0[kStep], x1[kStep], w0[kStep], w1[kStep];
+  // a wavefront takes U rows one band stride apart
+  const int first0 = xcd * rpx + bl * WPB + wid;
+  const int rstep = U * stride;
+  // software pipeline: the row pointers of the next row group are loaded while
+  // the current group gathers, and every load of a group that does not depend
+  // on its gathers (own X row, old Y and P, the first index chunk) is issued
+  // before the gathers, so a group costs about three memory latencies
+  int lo_n[U], hi_n[U];
 #pragma unroll
-        for (int q = 0; q < kStep; ++q) {
-          const int j0 = __builtin_amdgcn_readlane(jv0, k0 + q);
-          const int j1 = __builtin_amdgcn_readlane(jv1, k0 + q);
-          w0[q] = readlane_d(vv0, k0 + q);
-          w1[q] = readlane_d(vv1, k0 + q);
-          x0[q] = X[(size_t)j0 * ldx + cx];
-          x1[q] = X[(size_t)j1 * ldx + cx];
-        }
+  for (int u = 0; u < U; ++u) {
+    const int r = first0 + u * stride;
+    lo_n[u] = r < rhi ? rowptr[r] : 0;
+    hi_n[u] = r < rhi ? rowptr[r + 1] : 0;
+  }
+  for (int row0 = first0; row0 < rhi; row0 += rstep) {
+    int row[U], lo[U], hi[U];
+    bool ok[U];
+    double xi[U], acc[U], yo[U], po[U], dg[U];
 #pragma unroll
-        for (int q = 0; q < kStep; ++q) {
-          if (EDGE) {
-            a0 += w0[q] * (xi0 - x0[q]);
-            a1 += w1[q] * (xi1 - x1[q]);
-          } else {
-            a0 += w0[q] * x0[q];
-            a1 += w1[q] * x1[q];
-          }
-        }
-      }
+    for (int u = 0; u < U; ++u) {
+      row[u] = row0 + u * stride;
+      ok[u] = row[u] < rhi;
+      lo[u] = lo_n[u];
+      hi[u] = hi_n[u];
+      // own-row reads only for square forms (edge form, fused CG): X has
+      // n_cols rows, which may be fewer than n_rows otherwise
+      const size_t rx = (size_t)(ok[u] ? row[u] : 0);
+      xi[u] = (EDGE || FUSE) ? X[rx * ldx + cx] : 0.0;
+      dg[u] = EDGE ? diag[rx] : 0.0;
+      // P and Y stream through once: non-temporal, so they do not evict the
+      // gathered rows of X from L2
+      yo[u] = (FUSE && !first) ? __builtin_nontemporal_load(Y + rx * ldy + cx) : 0.0;
+      po[u] = (FUSE && !first) ? __builtin_nontemporal_load(P + rx * ldp + cx) : 0.0;
+      acc[u] = 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int row = u ? row1 : row0;
-      if ((u == 0 || ok1) && cok) {
-        const double xi = u ? xi1 : xi0;
-        double y = EDGE ? diag[row] * xi + (u ? a1 : a0) : (u ? a1 : a0);
-        const size_t iy = (size_t)row * ldy + cc;
+    for (int u = 0; u < U; ++u) {
+      const int r = row[u] + rstep;
+      lo_n[u] = r < rhi ? rowptr[r] : 0;
+      hi_n[u] = r < rhi ? rowptr[r + 1] : 0;
+    }
+    for (int base = 0;; base += kWave) {
+      int m = 0;
+      int jv[U];
+      double vv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int nu = max(0, min(kWave, hi[u] - lo[u] - base));
+        m = max(m, nu);
+        jv[u] = lane < nu ? col[lo[u] + base + lane] : 0;
+        vv[u] = lane < nu ? val[lo[u] + base + lane] : 0.0;
+      }
+      if (m == 0) break;
+      // steps of STEP slots with a fixed trip count, so all U * STEP gathers
+      // of a step are in flight together (padding slots carry weight 0)
+      for (int k0 = 0; k0 < m; k0 += STEP) {
+        double xs[U][STEP], ws[U][STEP];
+#pragma unroll
+        for (int q = 0; q < STEP; ++q)
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int j = __builtin_amdgcn_readlane(jv[u], k0 + q);
+            ws[u][q] = readlane_d(vv[u], k0 + q);
+            xs[u][q] = X[(size_t)j * ldx + cx];
+          }
+#pragma unroll
+        for (int q = 0; q < STEP; ++q)
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            acc[u] += EDGE ? ws[u][q] * (xi[u] - xs[u][q]) : ws[u][q] * xs[u][q];
+      }
+      if (m < kWave) break;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (ok[u] && cok) {
+        double y = EDGE ? dg[u] * xi[u] + acc[u] : acc[u];
+        const size_t iy = (size_t)row[u] * ldy + cc;
         if (FUSE) {
-          const size_t ip = (size_t)row * ldp + cc;
+          const size_t ip = (size_t)row[u] * ldp + cc;
           double pn;
           if (first) {
-            pn = X[(size_t)row * ldx + cc];
+            pn = xi[u];
           } else {
-            y += bt * Y[iy];
-            pn = X[(size_t)row * ldx + cc] + bt * P[ip];
+            y += bt * yo[u];
+            pn = xi[u] + bt * po[u];
           }
-          P[ip] = pn;
+          __builtin_nontemporal_store(pn, P + ip);
           dsum += pn * y;
         }
-        Y[iy] = y;
+        __builtin_nontemporal_store(y, Y + iy);
       }
     }
   }
@@ -241,18 +272,20 @@ __global__ __launch_bounds__(kBlock) void k_spmm_r64(
   }
 }
 
-int launch_spmm_r64(const CsrView& A, const double* X, int ldx, double* Y, int ldy, int b,
-                    hipStream_t s, bool fuse, bool first, const double* beta, double* P,
-                    int ldp, double* partial) {
+template <int U, int STEP>
+int launch_r64_t(const CsrView& A, const double* X, int ldx, double* Y, int ldy, int b,
+                 hipStream_t s, bool fuse, bool first, const double* beta, double* P, int ldp,
+                 double* partial) {
   constexpr int WPB = kBlock / kWave;
-  int gx = std::max(1, ceil_div(A.n_rows, 2 * WPB));
+  int gx = std::max(1, ceil_div(A.n_rows, U * WPB));
   if (fuse && partial) gx = std::min(gx, kRedBlocks);
   if (gx >= 8) gx = gx / 8 * 8;  // whole XCD rounds
   dim3 grid(gx, ceil_div(b, kWave));
   const bool edge = A.diag != nullptr;
-#define MMD_R64_CASE(E, F)                                                                  \
-  hipLaunchKernelGGL((k_spmm_r64<E, F>), grid, dim3(kBlock), 0, s, A.n_rows, A.rowptr, A.col, \
-                     A.val, A.diag, X, ldx, Y, ldy, b, first ? 1 : 0, beta, P, ldp, partial)
+#define MMD_R64_CASE(E, F)                                                                   \
+  hipLaunchKernelGGL((k_spmm_r64<E, F, U, STEP>), grid, dim3(kBlock), 0, s, A.n_rows, A.rowptr, \
+                     A.col, A.val, A.diag, X, ldx, Y, ldy, b, first ? 1 : 0, beta, P, ldp,     \
+                     partial)
   if (edge) {
     if (fuse) MMD_R64_CASE(true, true);
     else MMD_R64_CASE(true, false);
@@ -263,6 +296,14 @@ int launch_spmm_r64(const CsrView& A, const double* X, int ldx, double* Y, int l
 #undef MMD_R64_CASE
   check_launch();
   return gx;
+}
+
+int launch_spmm_r64(const CsrView& A, const double* X, int ldx, double* Y, int ldy, int b,
+                    hipStream_t s, bool fuse, bool first, const double* beta, double* P,
+                    int ldp, double* partial) {
+  // two rows in flight, gathers in steps of 4 slots: measured best of
+  // 1-4 rows x 2-8 slots, with adjacent or band-strided rows
+  return launch_r64_t<2, 4>(A, X, ldx, Y, ldy, b, s, fuse, first, beta, P, ldp, partial);
 }
 
 template <int LPR, int CT>

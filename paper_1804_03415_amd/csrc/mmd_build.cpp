@@ -521,16 +521,86 @@ HostCSR psi_localized(const HostCSR& A, const Patches& P, const std::vector<doub
 
 }  // namespace
 
-// Renumber level 0 patch-major: patches in id order, members ascending.  The
-// SpMM gathers of level 0 then touch nearby rows (L2 reuse) and every patch
-// is a contiguous index range.  The first-level patches are rewritten in the
-// new numbering; the caller's numbering is restored at the API boundary.
+// Renumber level 0 patch-major: patches in reverse Cuthill-McKee order of the
+// patch graph, members ascending.  The SpMM gathers of level 0 then touch
+// nearby rows (L2 reuse) and every patch is a contiguous index range; patch
+// ids (the level-1 numbering) do not change.  The first-level patches are
+// rewritten in the new numbering; the caller's numbering is restored at the
+// API boundary.
+// Reverse Cuthill-McKee order of the patch graph (patches adjacent when an
+// entry of A joins them): breadth-first from a pseudo-peripheral patch of each
+// component, neighbours by ascending degree, reversed.  Neighbouring patches
+// end up close in the order, so the rows a block or an XCD sweeps gather
+// from a narrow band of rows.
+std::vector<int> patch_rcm(const HostCSR& A, const Patches& P) {
+  const int m = static_cast<int>(P.size());
+  std::vector<int> pid(A.n_rows);
+  for (int j = 0; j < m; ++j)
+    for (int v : P[j]) pid[v] = j;
+  std::vector<std::vector<int>> adj(m);
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int j = 0; j < m; ++j) {
+    std::vector<int> s;
+    for (int v : P[j])
+      for (int64_t q = A.ptr[v]; q < A.ptr[v + 1]; ++q) {
+        const int t = pid[A.col[q]];
+        if (t != j) s.push_back(t);
+      }
+    std::sort(s.begin(), s.end());
+    s.erase(std::unique(s.begin(), s.end()), s.end());
+    adj[j] = std::move(s);
+  }
+  auto deg = [&](int j) { return static_cast<int>(adj[j].size()); };
+  std::vector<int> level(m, -1), order;
+  order.reserve(m);
+  std::vector<char> done(m, 0);
+  auto bfs = [&](int root, std::vector<int>& out) {  // plain BFS, returns last level's node
+    out.clear();
+    out.push_back(root);
+    level[root] = 0;
+    for (size_t h = 0; h < out.size(); ++h)
+      for (int t : adj[out[h]])
+        if (level[t] < 0) {
+          level[t] = level[out[h]] + 1;
+          out.push_back(t);
+        }
+    int far = out.back();
+    for (int v : out) {
+      if (level[v] == level[far] && deg(v) < deg(far)) far = v;
+      level[v] = -1;
+    }
+    return far;
+  };
+  std::vector<int> comp;
+  for (int r = 0; r < m; ++r) {
+    if (done[r]) continue;
+    // pseudo-peripheral start: two sweeps from r
+    int a = bfs(r, comp);
+    a = bfs(a, comp);
+    const size_t first = order.size();
+    order.push_back(a);
+    done[a] = 1;
+    for (size_t h = first; h < order.size(); ++h) {
+      std::vector<int> nb;
+      for (int t : adj[order[h]])
+        if (!done[t]) {
+          done[t] = 1;
+          nb.push_back(t);
+        }
+      std::stable_sort(nb.begin(), nb.end(), [&](int x, int y) { return deg(x) < deg(y); });
+      order.insert(order.end(), nb.begin(), nb.end());
+    }
+    std::reverse(order.begin() + first, order.end());
+  }
+  return order;
+}
+
 void renumber_level0(mmd_handle& h, Patches& P) {
   LevelHost& L0 = h.host[0];
   const int n = L0.n;
   std::vector<int> perm;
   perm.reserve(n);
-  for (auto& m : P) perm.insert(perm.end(), m.begin(), m.end());
+  for (int j : patch_rcm(L0.A, P)) perm.insert(perm.end(), P[j].begin(), P[j].end());
   std::vector<int> iperm(n);
   for (int i = 0; i < n; ++i) iperm[perm[i]] = i;
   h.A_user = L0.A;
