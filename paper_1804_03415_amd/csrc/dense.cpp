@@ -106,14 +106,22 @@ void tridiag_eig(int n, const double* din, const double* ein, std::vector<double
   std::vector<double> e(n, 0.0);
   for (int i = 0; i + 1 < n; ++i) e[i] = ein[i];
   const double eps = std::numeric_limits<double>::epsilon();
-  // rotate pairs of columns (i, i+1) of Z = pairs of entries in each tracked row
+  // rotations act on pairs of columns (i, i+1) of the tracked rows; they are
+  // applied to a transposed copy, where each column is a contiguous row
+  std::vector<double> zt;
+  if (track) {
+    zt.resize((size_t)n * ntrack);
+    for (int r = 0; r < ntrack; ++r)
+      for (int j = 0; j < n; ++j) zt[(size_t)j * ntrack + r] = track[(size_t)r * n + j];
+  }
   auto rot = [&](int i, double c, double s) {
     if (!track) return;
+    double* zi = zt.data() + (size_t)i * ntrack;
+    double* zj = zi + ntrack;
     for (int r = 0; r < ntrack; ++r) {
-      double* z = track + (size_t)r * n;
-      const double h = z[i + 1];
-      z[i + 1] = s * z[i] + c * h;
-      z[i] = c * z[i] - s * h;
+      const double h = zj[r];
+      zj[r] = s * zi[r] + c * h;
+      zi[r] = c * zi[r] - s * h;
     }
   };
   double f = 0.0, tst = 0.0;
@@ -166,14 +174,11 @@ void tridiag_eig(int n, const double* din, const double* ein, std::vector<double
   std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return d[a] < d[b]; });
   w.resize(n);
   for (int j = 0; j < n; ++j) w[j] = d[idx[j]];
-  if (track) {
-    std::vector<double> tmp(n);
-    for (int r = 0; r < ntrack; ++r) {
-      double* z = track + (size_t)r * n;
-      for (int j = 0; j < n; ++j) tmp[j] = z[idx[j]];
-      std::copy(tmp.begin(), tmp.end(), z);
+  if (track)
+    for (int j = 0; j < n; ++j) {
+      const double* src = zt.data() + (size_t)idx[j] * ntrack;
+      for (int r = 0; r < ntrack; ++r) track[(size_t)r * n + j] = src[r];
     }
-  }
 }
 
 void sym_eig(int n, const double* a_in, std::vector<double>& w, std::vector<double>* z) {
