@@ -2,7 +2,9 @@
 // (host-driven control flow, many small kernels and host round trips), are
 // overlapped by running several of them at once on separate HIP streams, one
 // host thread per stream.  Problems are handed out largest first (nnz x nev),
-// so the long ones start early and the short ones fill the tail.
+// so the long ones start early and the short ones fill the tail.  The
+// persistent single-vector solvers run one at a time across the batch (a
+// process-wide lock around each launch), everything else overlaps freely.
 #include <algorithm>
 #include <atomic>
 #include <mutex>
@@ -68,7 +70,7 @@ void leftmost_batched(int B, mmd_handle* const* hs, const int* nev, double tol,
         const int b = order[i];
         try {
           Solver sv(*hs[b], s, o, st ? &st[b] : nullptr);
-          sv.set_persistent(false);
+          sv.set_serialize_persistent(true);
           sv.leftmost(nev[b], tol, evals[b], evecs[b]);
         } catch (const Error& e) {
           fail(e.code, "problem " + std::to_string(b) + ": " + e.what());

@@ -403,10 +403,17 @@ bool Solver::pcg_single(int k, const double* B, double* X, double tol, bool use_
     }
     plan = &it->second;
   }
-  pcg1(a, s_, plan);
-  hi_.ensure(4);
-  d2h(hi_.p, a.out, 3);
-  sync();
+  {
+    // inside a batch, at most one persistent kernel is in flight on the
+    // device: its grid barrier then only ever waits for workgroups held back
+    // by finite kernels of other streams, never by another barrier
+    std::unique_lock<std::mutex> g(coop_mutex(), std::defer_lock);
+    if (serialize_coop_) g.lock();
+    pcg1(a, s_, plan);
+    hi_.ensure(4);
+    d2h(hi_.p, a.out, 3);
+    sync();
+  }
   MMD_REQUIRE(hi_.p[2] != 1, MMD_ENOTSPD, "PCG curvature p^T A p <= 0");
   MMD_REQUIRE(hi_.p[2] != 2, MMD_ENOCONV, "PCG reached the iteration cap");
   if (st_ && k > 0) st_->cg_M_iters[k] += hi_.p[1];

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -41,6 +42,12 @@ class Solver {
   // cooperative persistent ones (needed when other streams run concurrently:
   // a grid barrier must never wait on workgroups that cannot be resident)
   void set_persistent(bool on) { use_persistent_ = on; }
+  // serialise the persistent kernels of concurrent solvers (see pcg_single)
+  void set_serialize_persistent(bool on) { serialize_coop_ = on; }
+  static std::mutex& coop_mutex() {
+    static std::mutex m;
+    return m;
+  }
 
   // building blocks exposed through mmd_apply / mmd_solve
   void apply_op(int level, int op, const double* X, double* Y, int b);
@@ -139,6 +146,7 @@ class Solver {
   HBuf<int> hi_;
   int inner_iters_ = 16;
   bool use_persistent_ = true;
+  bool serialize_coop_ = false;
   std::map<int, Pcg1Plan> plans_;  // resident plain-CG plan per level (level 0)
   double norm_a0_ = 0.0;           // ||A||_inf of level 0 (mixed-precision floor test)
   std::vector<double> tpcg_;       // relative PCG tolerance per level (k >= 1)
