@@ -29,11 +29,16 @@ struct Pcg1Args {
 // rp of its row pointers).  resident == false: A does not fit, use k_pcg1.
 struct Pcg1Plan {
   bool resident = false;
+  bool flex = false;  // resident flexible PCG (A and M slices in LDS)
   int grid = 0;
   size_t lds = 0;
   DBuf<int> part;  // grid + 1 row boundaries
 };
 void pcg1_plan(const CsrView& A, const std::vector<int>& rp, Pcg1Plan& plan);
+// Plan for the resident flexible PCG on (A, M) (host row pointers rpa, rpm):
+// the fewest blocks (multiple of 8, at least 16) whose slices fit in LDS.
+void pcg1_plan_flex(const CsrView& A, const std::vector<int>& rpa, const CsrView& M,
+                    const std::vector<int>& rpm, Pcg1Plan& plan);
 
 // Launch on stream s (asynchronous).  Stop rule ||r|| <= tol ||b||; the inner
 // CG stops at ||r_in|| <= tol_in ||r||.  Plain CG (no M) runs the resident

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 
 #include "common.h"
@@ -495,6 +496,223 @@ __global__ __launch_bounds__(kThreads) void k_cg1_res(Pcg1Args a, const int* __r
   }
 }
 
+// ---------------------------------------------------------------------------
+// Resident flexible PCG (levels k >= 1): the block's rows of A^(k) and M^(k)
+// both live in LDS, the row state (x, r, z, z_old, p, q and the inner
+// ri, pi, qi) in registers; only z (gathered by A z) and ri (gathered by
+// M ri) go through global memory.  Coarse rows hold tens of entries, so
+// kLpr lanes share a row (strided over its entries, combined with xor
+// shuffles); every lane of the group keeps the row's state, lane 0 of the
+// group writes it out and contributes it to the dot products.  Same
+// arithmetic as k_pcg1's flexible branch: Polak-Ribiere beta, inner CG on M
+// from zero to tol_in ||r||.
+constexpr int kLpr = 8;
+constexpr int kSlots = kThreads / kLpr;  // rows per pass
+constexpr int kMaxU2 = 2;                // passes: rows per block <= 256
+
+// (B x)_l for local row l (all lanes of the group call it; invalid rows give 0)
+__device__ inline double row_lpr(bool ok, int l, int sub, const int* lrp, const int* lcol,
+                                 const double* lval, const double* x) {
+  double acc = 0.0;
+  if (ok)
+    for (int k = lrp[l] + sub; k < lrp[l + 1]; k += kLpr) acc += lval[k] * x[lcol[k]];
+#pragma unroll
+  for (int off = 1; off < kLpr; off <<= 1) acc += __shfl_xor(acc, off, kWave);
+  return acc;
+}
+
+__global__ __launch_bounds__(kThreads) void k_pcg1_res(Pcg1Args a, const int* __restrict__ part) {
+  extern __shared__ double lds[];
+  __shared__ double sh[kThreads / kWave];
+  const int bx = (gridDim.x % 8) ? (int)blockIdx.x
+                                 : (int)((blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8);
+  Ctx c{a.bar, 0u, (int)gridDim.x, (int)blockIdx.x, 0, 0, 0, 0, (int)(threadIdx.x & (kWave - 1)),
+        a.red, 0};
+  const CsrView& A = a.A;
+  const CsrView& M = a.M;
+  const int r0 = part[bx], r1 = part[bx + 1], nr = r1 - r0;
+  const int ea = A.rowptr[r0], na = A.rowptr[r1] - ea;
+  const int em = M.rowptr[r0], nm = M.rowptr[r1] - em;
+  double* aval = lds;
+  double* mval = aval + na;
+  int* arp = reinterpret_cast<int*>(mval + nm);
+  int* mrp = arp + nr + 1;
+  int* acol = mrp + nr + 1;
+  int* mcol = acol + na;
+  for (int t = threadIdx.x; t < na; t += kThreads) {
+    aval[t] = A.val[ea + t];
+    acol[t] = A.col[ea + t];
+  }
+  for (int t = threadIdx.x; t < nm; t += kThreads) {
+    mval[t] = M.val[em + t];
+    mcol[t] = M.col[em + t];
+  }
+  for (int t = threadIdx.x; t <= nr; t += kThreads) {
+    arp[t] = A.rowptr[r0 + t] - ea;
+    mrp[t] = M.rowptr[r0 + t] - em;
+  }
+  __syncthreads();
+  const int sub = threadIdx.x % kLpr, slot = threadIdx.x / kLpr;
+  const bool lead = sub == 0;
+  double* zg = a.z;    // gathered by A z
+  double* rig = a.ri;  // gathered by M ri
+  double x[kMaxU2], r[kMaxU2], z[kMaxU2], zo[kMaxU2], p[kMaxU2], q[kMaxU2];
+  double ri[kMaxU2], pi[kMaxU2], qi[kMaxU2];
+  bool ok[kMaxU2];
+  int lrow[kMaxU2];
+  double pb = 0.0, prr0 = 0.0;
+#pragma unroll
+  for (int u = 0; u < kMaxU2; ++u) {
+    x[u] = r[u] = z[u] = zo[u] = p[u] = q[u] = ri[u] = pi[u] = qi[u] = 0.0;
+    lrow[u] = slot + u * kSlots;
+    ok[u] = lrow[u] < nr;
+    if (ok[u]) {
+      const double bi = a.b[r0 + lrow[u]];
+      if (lead) pb += bi * bi;
+      if (a.use_x0)
+        x[u] = a.x[r0 + lrow[u]];
+      else
+        r[u] = bi;
+    }
+  }
+  if (a.use_x0) {
+#pragma unroll
+    for (int u = 0; u < kMaxU2; ++u) {
+      const double w = row_lpr(ok[u], lrow[u], sub, arp, acol, aval, a.x);
+      if (ok[u]) {
+        r[u] = a.b[r0 + lrow[u]] - w;
+        if (lead) prr0 += r[u] * r[u];
+      }
+    }
+  } else {
+    prr0 = pb;
+  }
+  double bn2, rr2;
+  grid_sum2(c, pb, prr0, sh, bn2, rr2);
+  const double tol2 = a.tol * a.tol * bn2;
+  const double tol_in2 = a.tol_in * a.tol_in;
+  int it = 0, inner_total = 0, flag = 0;
+  bool done = !(bn2 > 0.0) || rr2 <= tol2;
+  // z = M^-1 r approximately (inner CG from zero); z ends in registers and zg
+  auto inner = [&](double rnorm2) {
+#pragma unroll
+    for (int u = 0; u < kMaxU2; ++u) {
+      z[u] = 0.0;
+      ri[u] = r[u];
+      if (ok[u] && lead) rig[r0 + lrow[u]] = ri[u];
+    }
+    grid_barrier(c);
+    double rri = rnorm2, bi = 0.0;
+    bool f = true;
+    int k = 0;
+    while (rri > tol_in2 * rnorm2 && k < a.maxit_in) {
+      double ppq = 0.0;
+#pragma unroll
+      for (int u = 0; u < kMaxU2; ++u) {
+        const double w = row_lpr(ok[u], lrow[u], sub, mrp, mcol, mval, rig);
+        if (ok[u]) {
+          pi[u] = f ? ri[u] : ri[u] + bi * pi[u];
+          qi[u] = f ? w : w + bi * qi[u];
+          if (lead) ppq += pi[u] * qi[u];
+        }
+      }
+      f = false;
+      const double pq = grid_sum(c, ppq, sh);
+      if (!(pq > 0.0)) break;
+      const double al = rri / pq;
+      double prr = 0.0;
+#pragma unroll
+      for (int u = 0; u < kMaxU2; ++u) {
+        if (ok[u]) {
+          z[u] += al * pi[u];
+          ri[u] -= al * qi[u];
+          if (lead) {
+            rig[r0 + lrow[u]] = ri[u];
+            prr += ri[u] * ri[u];
+          }
+        }
+      }
+      const double rn = grid_sum(c, prr, sh);
+      bi = rn / rri;
+      rri = rn;
+      ++k;
+    }
+#pragma unroll
+    for (int u = 0; u < kMaxU2; ++u)
+      if (ok[u] && lead) zg[r0 + lrow[u]] = z[u];
+    inner_total += k;
+  };
+  if (!done) {
+    inner(rr2);
+    double prz = 0.0;
+#pragma unroll
+    for (int u = 0; u < kMaxU2; ++u)
+      if (ok[u] && lead) prz += r[u] * z[u];
+    double rz = grid_sum(c, prz, sh);
+    double beta = 0.0;
+    bool first = true;
+    while (true) {
+      double ppq = 0.0;
+#pragma unroll
+      for (int u = 0; u < kMaxU2; ++u) {
+        const double w = row_lpr(ok[u], lrow[u], sub, arp, acol, aval, zg);
+        if (ok[u]) {
+          p[u] = first ? z[u] : z[u] + beta * p[u];
+          q[u] = first ? w : w + beta * q[u];
+          if (lead) ppq += p[u] * q[u];
+        }
+      }
+      first = false;
+      const double pq = grid_sum(c, ppq, sh);
+      if (!(pq > 0.0)) {
+        flag = 1;
+        break;
+      }
+      const double al = rz / pq;
+      double prr = 0.0;
+#pragma unroll
+      for (int u = 0; u < kMaxU2; ++u) {
+        if (ok[u]) {
+          x[u] += al * p[u];
+          r[u] -= al * q[u];
+          zo[u] = z[u];
+          if (lead) prr += r[u] * r[u];
+        }
+      }
+      const double rn = grid_sum(c, prr, sh);
+      ++it;
+      rr2 = rn;
+      if (rn <= tol2) break;
+      if (it >= a.maxit) {
+        flag = 2;
+        break;
+      }
+      inner(rn);
+      double p1 = 0.0, p2 = 0.0;
+#pragma unroll
+      for (int u = 0; u < kMaxU2; ++u)
+        if (ok[u] && lead) {
+          p1 += r[u] * z[u];
+          p2 += r[u] * zo[u];
+        }
+      double rzn, rzo;
+      grid_sum2(c, p1, p2, sh, rzn, rzo);
+      beta = (rzn - rzo) / rz;
+      rz = rzn;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kMaxU2; ++u)
+    if (ok[u] && lead) a.x[r0 + lrow[u]] = x[u];
+  if (bx == 0 && threadIdx.x == 0) {
+    a.out[0] = it;
+    a.out[1] = inner_total;
+    a.out[2] = flag;
+    a.res[0] = rr2;
+    a.res[1] = bn2;
+  }
+}
+
 int lanes_for(double avg) {
   if (avg <= 10.0) return 8;
   if (avg <= 24.0) return 16;
@@ -525,11 +743,12 @@ int pcg1_grid() {
 void pcg1(Pcg1Args a, hipStream_t s, const Pcg1Plan* plan) {
   MMD_HIP(hipMemsetAsync(a.bar, 0, sizeof(unsigned), s));
   void* args[] = {&a};
-  if (plan && plan->resident && !a.M.rowptr) {
+  if (plan && plan->resident && (a.M.rowptr != nullptr) == plan->flex) {
     const int* part = plan->part.p;
     void* rargs[] = {&a, &part};
-    MMD_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_cg1_res),
-                                       dim3(plan->grid), dim3(kThreads), rargs,
+    const void* fn = plan->flex ? reinterpret_cast<const void*>(k_pcg1_res)
+                                : reinterpret_cast<const void*>(k_cg1_res);
+    MMD_HIP(hipLaunchCooperativeKernel(fn, dim3(plan->grid), dim3(kThreads), rargs,
                                        static_cast<unsigned>(plan->lds), s));
     return;
   }
@@ -593,6 +812,63 @@ void pcg1_plan(const CsrView& A, const std::vector<int>& rp, Pcg1Plan& plan) {
   MMD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cg1_res, kThreads, lds));
   int cus = 0;
   MMD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  if (per <= 0 || grid > per * cus) return;
+  plan.part.ensure(grid + 1);
+  MMD_HIP(hipMemcpy(plan.part.p, part.data(), sizeof(int) * (grid + 1), hipMemcpyHostToDevice));
+  plan.grid = grid;
+  plan.lds = lds;
+  plan.resident = true;
+}
+
+void pcg1_plan_flex(const CsrView& A, const std::vector<int>& rpa, const CsrView& M,
+                    const std::vector<int>& rpm, Pcg1Plan& plan) {
+  plan.resident = false;
+  plan.flex = true;
+  const int n = A.n_rows;
+  if (n == 0 || (int)rpa.size() != n + 1 || (int)rpm.size() != n + 1 || M.n_rows != n) return;
+  if (const char* e = std::getenv("MMDEIG_NO_RESIDENT"))
+    if (std::atoi(e) != 0) return;
+  int dev = 0;
+  MMD_HIP(hipGetDevice(&dev));
+  int maxsh = 0, cus = 0;
+  MMD_HIP(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  MMD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const size_t avail = static_cast<size_t>(maxsh) - sizeof(double) * (kThreads / kWave) - 256;
+  const double tot_bytes = 12.0 * (rpa[n] + rpm[n]) + 8.0 * n;
+  const int max_rows = kMaxU2 * kSlots;
+  int grid = std::max(16, (n + max_rows - 1) / max_rows);
+  grid = std::max(grid, static_cast<int>(std::ceil(tot_bytes / (0.95 * avail))));
+  grid = (grid + 7) / 8 * 8;
+  // balance entries of A and M plus rows
+  const double tot = static_cast<double>(rpa[n]) + rpm[n] + n;
+  std::vector<int> part;
+  size_t lds = 0;
+  for (; grid <= 4 * cus; grid += 8) {
+    part.assign(grid + 1, n);
+    part[0] = 0;
+    int i = 0;
+    for (int j = 1; j < grid; ++j) {
+      const double target = tot * j / grid;
+      while (i < n && static_cast<double>(rpa[i]) + rpm[i] + i < target) ++i;
+      part[j] = i;
+    }
+    lds = 0;
+    int mr = 0;
+    for (int j = 0; j < grid; ++j) {
+      const int nr = part[j + 1] - part[j];
+      const size_t ne = static_cast<size_t>(rpa[part[j + 1]] - rpa[part[j]]) +
+                        static_cast<size_t>(rpm[part[j + 1]] - rpm[part[j]]);
+      lds = std::max(lds, ne * 12 + 8 * static_cast<size_t>(nr + 1));
+      mr = std::max(mr, nr);
+    }
+    if (lds <= avail && mr <= max_rows) break;
+  }
+  if (grid > 4 * cus) return;
+  lds = (lds + 255) / 256 * 256;
+  MMD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_pcg1_res),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  int per = 0;
+  MMD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_pcg1_res, kThreads, lds));
   if (per <= 0 || grid > per * cus) return;
   plan.part.ensure(grid + 1);
   MMD_HIP(hipMemcpy(plan.part.p, part.data(), sizeof(int) * (grid + 1), hipMemcpyHostToDevice));

@@ -392,14 +392,21 @@ bool Solver::pcg_single(int k, const double* B, double* X, double tol, bool use_
   a.out = pool_.i("p1:out", 3);
   a.res = pool_.d("p1:res", 2);
   const Pcg1Plan* plan = nullptr;
-  if (k == 0) {
+  {
     auto it = plans_.find(k);
     if (it == plans_.end()) {
       std::vector<int> rp(n + 1);
       d2h(rp.data(), a.A.rowptr, n + 1);
       sync();
       it = plans_.emplace(k, Pcg1Plan()).first;
-      pcg1_plan(a.A, rp, it->second);
+      if (k == 0) {
+        pcg1_plan(a.A, rp, it->second);
+      } else {
+        std::vector<int> rpm(n + 1);
+        d2h(rpm.data(), a.M.rowptr, n + 1);
+        sync();
+        pcg1_plan_flex(a.A, rp, a.M, rpm, it->second);
+      }
     }
     plan = &it->second;
   }
