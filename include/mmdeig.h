@@ -166,10 +166,11 @@ int eig_leftmost(mmd_handle* h, int32_t nev, double tol, const eig_opts* opts,
  * opts->streams problems in flight at a time, each on its own HIP stream
  * driven by its own host thread, largest nnz x nev first.  Work on the
  * caller's stream that precedes the call is waited for; the results are
- * complete when the call returns.  Within a batch the single-vector solves
- * use block kernels rather than the cooperative persistent ones, which need
- * the whole device.  st: NULL or an array of B counters.  The first error of
- * any problem is returned (the others are still finished). */
+ * complete when the call returns.  Within a batch the persistent
+ * single-vector solvers (cooperative launches with a grid barrier) run one at
+ * a time; all other work of the problems overlaps.  st: NULL or an array of B
+ * counters.  The first error of any problem is returned (the others are
+ * still finished). */
 int eig_leftmost_batched(int32_t B, mmd_handle* const* hs, const int32_t* nev, double tol,
                          const eig_opts* opts, double* const* evals, double* const* evecs,
                          eig_stats* st, void* hip_stream);
