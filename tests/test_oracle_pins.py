@@ -350,3 +350,17 @@ def test_grid3d_constant_coefficient_closed_form():
     s = 4 * np.sin(j * np.pi / (2 * (m + 1))) ** 2
     ref = np.sort((s[:, None, None] + s[None, :, None] + s[None, None, :]).ravel())[:20]
     assert np.max(np.abs(lam - ref) / ref) < 1e-10
+
+
+def test_oracle_grid2d_32_golden():
+    """The oracle's 50 smallest pairs of the 32 x 32 grid (3 levels, exact Psi)
+    against the stored closed-form values (tests/golden/grid2d_32_nev50.txt);
+    lambda_50 < lambda_51 with a 2.4% gap, so the set is well defined."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "grid2d_32_nev50.txt")
+    ref = np.loadtxt(path)
+    assert ref.size == 51 and (ref[50] - ref[49]) / ref[49] > 0.02
+    p = wl.grid2d(32)
+    lam, V = krylov.eig_leftmost(p.scipy(), 50, 1e-10, mmd_kwargs=dict(
+        grid=p.grid, levels=3, exact_max_n=4096))
+    assert np.max(np.abs(lam - ref[:50]) / ref[:50]) < 1e-10
