@@ -950,6 +950,9 @@ void Solver::extend(int k, double*& V, std::vector<double>& D, int& m, int m_tar
     tri_of(L.T, L.cap, L.j, dd, ee);
     dense::tridiag_eig(L.j, dd.data(), ee.data(), th, nullptr, 0);
     const double mu_hat = th[std::min(d, kcur) - 1];
+    if (log_on())
+      std::fprintf(stderr, "[mmdeig] extend L%d explored %d of %d, restarts %d, mu_hat %.6g\n",
+                   k, kcur, want, restarts, mu_hat);
     if (mu_hat < mu_ex || kcur >= want || kcur >= cap) break;
   }
   const int mnew = kcur;
