@@ -128,10 +128,10 @@ __global__ __launch_bounds__(kBlock) void k_spmm(
 }
 
 // Blocks of more than 32 columns: one wavefront per (row, 64-column tile),
-// two rows per wavefront in flight.  The lanes first load up to 64 of the
-// row's column indices and weights with one vector load, then broadcast them
-// with readlane, so every gather of the row is issued back to back instead of
-// waiting on its index load.  Slots past the end of a row's nonzeros gather
+// U rows per wavefront in flight (one at the launch used).  The lanes first
+// load up to 64 of the row's column indices and weights with one vector load,
+// then broadcast them with readlane, so the gathers of the row are issued in
+// steps of STEP without waiting on an index load each.  Slots past the end of a row's nonzeros gather
 // row 0 with weight 0.  Each XCD (workgroups are dealt round-robin to the
 // 8 XCDs) sweeps its own contiguous eighth of the rows.  Fused CG epilogue as
 // in k_spmm.
@@ -144,8 +144,11 @@ __device__ inline double readlane_d(double v, int k) {
   return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
 }
 
+// eight wavefronts per SIMD (at most 64 VGPRs): the kernel is bound by the
+// latency of its dependent load rounds, so resident waves count more than
+// rows in flight per wave
 template <bool EDGE, bool FUSE, int U, int STEP>
-__global__ __launch_bounds__(kBlock) void k_spmm_r64(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_spmm_r64(
     int n_rows, const int* __restrict__ rowptr, const int* __restrict__ col,
     const double* __restrict__ val, const double* __restrict__ diag,
     const double* __restrict__ X, int ldx, double* __restrict__ Y, int ldy, int b, int first,
@@ -301,9 +304,9 @@ int launch_r64_t(const CsrView& A, const double* X, int ldx, double* Y, int ldy,
 int launch_spmm_r64(const CsrView& A, const double* X, int ldx, double* Y, int ldy, int b,
                     hipStream_t s, bool fuse, bool first, const double* beta, double* P,
                     int ldp, double* partial) {
-  // two rows in flight, gathers in steps of 4 slots: measured best of
-  // 1-4 rows x 2-8 slots, with adjacent or band-strided rows
-  return launch_r64_t<2, 4>(A, X, ldx, Y, ldy, b, s, fuse, first, beta, P, ldp, partial);
+  // one row per wavefront, gathers in steps of 4 slots, 8 waves per SIMD:
+  // measured best of 1-4 rows x 2-8 slots at 5-8 waves per SIMD
+  return launch_r64_t<1, 4>(A, X, ldx, Y, ldy, b, s, fuse, first, beta, P, ldp, partial);
 }
 
 template <int LPR, int CT>
@@ -615,7 +618,34 @@ __global__ __launch_bounds__(1024) void k_cg_update(double* __restrict__ X, int 
     double acc = 0.0;
     if (m.act) {
       const double a = alpha[m.col];
-      for (int i = blockIdx.x * m.rstep + m.roff; i < n; i += gridDim.x * m.rstep) {
+      const int step = gridDim.x * m.rstep;
+      int i = blockIdx.x * m.rstep + m.roff;
+      // four rows per pass, all loads of a pass issued before its stores
+      constexpr int kU = 4;
+      for (; i + (kU - 1) * step < n; i += kU * step) {
+        double r[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) r[u] = R[(size_t)(i + u * step) * ld + m.col];
+        if (a != 0.0) {
+          double pv[kU], qv[kU], xv[kU];
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            const size_t idx = (size_t)(i + u * step) * ld + m.col;
+            pv[u] = P[idx];
+            qv[u] = Q[idx];
+            xv[u] = X[(size_t)(i + u * step) * ldx + m.col];
+          }
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            X[(size_t)(i + u * step) * ldx + m.col] = xv[u] + a * pv[u];
+            r[u] -= a * qv[u];
+            R[(size_t)(i + u * step) * ld + m.col] = r[u];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) acc += r[u] * r[u];
+      }
+      for (; i < n; i += step) {
         const size_t idx = (size_t)i * ld + m.col;
         double r = R[idx];
         if (a != 0.0) {
