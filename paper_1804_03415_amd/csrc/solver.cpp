@@ -266,7 +266,11 @@ void Solver::cg(int k, OpKind op, const double* B, int ldb, double* X, int ldx, 
   col_dot(R, b, R, b, n, b, p2, s_);
   cg_init(sc, p1, p2, nb, b, tol, parent, s_);
   MMD_HIP(hipMemsetAsync(sc.notspd, 0, sizeof(int), s_));
+  int64_t n_wide = 0, n_narrow = 0, col_iters = 0;
   auto iterate = [&](bool first) {
+    if (bc > 32) ++n_wide;
+    else ++n_narrow;
+    col_iters += bc;
     int np;
     if (csr) {
       // fused: P = R + beta P, Q = A R + beta Q (= A P), partial p.q per block
@@ -311,15 +315,16 @@ void Solver::cg(int k, OpKind op, const double* B, int ldb, double* X, int ldx, 
     sync();
     for (int c = 0; c < bc; ++c) it_host[cols[c]] = hi_.p[c];
   };
+  // The columns are checked on the host before the first step (columns whose
+  // start already meets the tolerance never iterate) and then every 8 steps
+  // (16 once the block is narrow); the working set is compacted as soon as an
+  // eighth of it has converged.  A compaction moves about as many bytes as
+  // one step, and the columns of a refinement block need from 0 to ~100
+  // steps each, so the width tracks the unconverged columns closely.
   const int maxit = 100000;
-  int done = 0, chunk = 4;
+  int done = 0;
   bool first = true;
   while (true) {
-    for (int t = 0; t < chunk; ++t) {
-      iterate(first);
-      first = false;
-    }
-    done += chunk;
     hi_.ensure(bc + 1);
     d2h(hi_.p, sc.active, bc);
     d2h(hi_.p + bc, sc.notspd, 1);
@@ -330,9 +335,8 @@ void Solver::cg(int k, OpKind op, const double* B, int ldb, double* X, int ldx, 
       if (hi_.p[c] != 0) keep.push_back(c);
     if (keep.empty()) break;
     MMD_REQUIRE(done < maxit, MMD_ENOCONV, "CG reached the iteration cap");
-    chunk = std::min(chunk * 2, 64);
     const int na = static_cast<int>(keep.size());
-    if (bc >= 16 && 4 * na <= 3 * bc) {
+    if (bc >= 16 && 8 * na <= 7 * bc) {
       take_iters();
       flush_x();
       ++stage;
@@ -345,8 +349,10 @@ void Solver::cg(int k, OpKind op, const double* B, int ldb, double* X, int ldx, 
       sc2.notspd = sc.notspd;
       h2d(d_idx, keep.data(), na);
       gather_cols(R, bc, d_idx, R2, na, n, na, s_);
-      gather_cols(P, bc, d_idx, P2, na, n, na, s_);
-      gather_cols(Q, bc, d_idx, Q2, na, n, na, s_);
+      if (!first) {  // before the first step P and Q hold nothing yet
+        gather_cols(P, bc, d_idx, P2, na, n, na, s_);
+        gather_cols(Q, bc, d_idx, Q2, na, n, na, s_);
+      }
       gather_cols(Xw, ldw, d_idx, X2, na, n, na, s_);
       gather_scalars(sc, sc2, d_idx, na, s_);
       sync();  // keep (host) must outlive its copy
@@ -361,9 +367,22 @@ void Solver::cg(int k, OpKind op, const double* B, int ldb, double* X, int ldx, 
       sc = sc2;
       bc = na;
     }
+    const int chunk = bc > 32 ? 8 : 16;
+    for (int t = 0; t < chunk; ++t) {
+      iterate(first);
+      first = false;
+    }
+    done += chunk;
   }
   take_iters();
   flush_x();
+  if (log_on() && k == 0 && op == OpKind::A && b > 32) {
+    std::vector<int> h = it_host;
+    std::sort(h.begin(), h.end());
+    std::fprintf(stderr, "[mmdeig] cg0 %s b %d iters min %d med %d max %d; steps wide %lld narrow %lld; column-steps %lld\n",
+                 tag.c_str(), b, h.front(), h[h.size() / 2], h.back(), (long long)n_wide,
+                 (long long)n_narrow, (long long)col_iters);
+  }
   if (iters) *iters = it_host;
 }
 
