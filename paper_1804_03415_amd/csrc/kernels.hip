@@ -620,31 +620,6 @@ __global__ __launch_bounds__(1024) void k_cg_update(double* __restrict__ X, int 
       const double a = alpha[m.col];
       const int step = gridDim.x * m.rstep;
       int i = blockIdx.x * m.rstep + m.roff;
-      // four rows per pass, all loads of a pass issued before its stores
-      constexpr int kU = 4;
-      for (; i + (kU - 1) * step < n; i += kU * step) {
-        double r[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) r[u] = R[(size_t)(i + u * step) * ld + m.col];
-        if (a != 0.0) {
-          double pv[kU], qv[kU], xv[kU];
-#pragma unroll
-          for (int u = 0; u < kU; ++u) {
-            const size_t idx = (size_t)(i + u * step) * ld + m.col;
-            pv[u] = P[idx];
-            qv[u] = Q[idx];
-            xv[u] = X[(size_t)(i + u * step) * ldx + m.col];
-          }
-#pragma unroll
-          for (int u = 0; u < kU; ++u) {
-            X[(size_t)(i + u * step) * ldx + m.col] = xv[u] + a * pv[u];
-            r[u] -= a * qv[u];
-            R[(size_t)(i + u * step) * ld + m.col] = r[u];
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) acc += r[u] * r[u];
-      }
       for (; i < n; i += step) {
         const size_t idx = (size_t)i * ld + m.col;
         double r = R[idx];
