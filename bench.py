@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-9)
     ap.add_argument("--levels", type=int, default=3)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32-refine"])
+    ap.add_argument("--alpha", type=float, default=3.0,
+                    help="refinement threshold factor: mu_re = alpha eps_(k+1)")
+    ap.add_argument("--beta", type=float, default=1.0,
+                    help="extension threshold factor: mu_ex = beta eps_k")
     ap.add_argument("--mixed-steps", type=int, default=1,
                     help="timed eigensolves of the FP32-CG + FP64-refinement form after the "
                          "main run (0: skip), compared pair by pair with the main run")
@@ -82,14 +86,16 @@ def cluster_angles(lam, V, W, gap=1e-6):
 def timed_solves(dec, a, precision, steps, warmup):
     import torch
     for w in range(warmup):
-        _, _, st = dec.eig_leftmost(a.nev, tol=a.tol, precision=precision)
+        _, _, st = dec.eig_leftmost(a.nev, tol=a.tol, precision=precision, alpha=a.alpha,
+                                    beta=a.beta)
         print("%s warmup %d: %.2f s" % (precision, w, st["seconds_total"]), file=sys.stderr,
               flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = []
     for s_ in range(steps):
-        lam, V, st = dec.eig_leftmost(a.nev, tol=a.tol, precision=precision)
+        lam, V, st = dec.eig_leftmost(a.nev, tol=a.tol, precision=precision, alpha=a.alpha,
+                                      beta=a.beta)
         stats.append(st)
         print("%s step %d: %.2f s" % (precision, s_, st["seconds_total"]), file=sys.stderr,
               flush=True)
@@ -367,8 +373,8 @@ def main():
         "dtype": "f32+f64" if fp32 else "f64",
         "data": "synthetic",
         "config": {"workload": "rgg_laplacian_n%d_nev%d" % (a.n, a.nev), "n": a.n,
-                   "nnz": int(p.nnz), "nev": a.nev, "tol": a.tol,
-                   "levels": info["sizes"], "build_s": round(t_build, 2)},
+                   "nnz": int(p.nnz), "nev": a.nev, "tol": a.tol, "alpha": a.alpha,
+                   "beta": a.beta, "levels": info["sizes"], "build_s": round(t_build, 2)},
         "max_rel_residual": float(rho.max()),
         "residual_ok": bool(rho.max() <= 1e-8),
         "null_cluster": ncomp_null,
