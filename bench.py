@@ -118,7 +118,7 @@ def measured_traffic():
     counter summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None
     when the kernel source has changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "spmm_r64_rgg_n1e5_traffic.json")
+    path = os.path.join(ROOT, "profiles", "spmm_tile_rgg_n1e5_traffic.json")
     try:
         with open(path) as f:
             d = json.load(f)
@@ -315,7 +315,8 @@ def main():
         None if fp32 else measured_traffic())
     roof = {"bound": "hbm",
             "kernel": ("k_spmm32_w<edge>: level-0 FP32 block-CG step" if fp32 else
-                       "k_spmm_r64<edge,fuse>: level-0 block-CG step P = R + beta P, "
+                       "k_spmm_tile<fuse> (LDS-staged 32-row tiles; k_spmm_r64 when the "
+                       "level is not tiled): level-0 block-CG step P = R + beta P, "
                        "Q = A R + beta Q, partial p.q") + " (block width %d..1)" % a.nev,
             "achieved": kr["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": kr["frac"], "traffic": traffic,

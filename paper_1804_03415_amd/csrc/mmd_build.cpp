@@ -600,7 +600,18 @@ void renumber_level0(mmd_handle& h, Patches& P) {
   const int n = L0.n;
   std::vector<int> perm;
   perm.reserve(n);
-  for (int j : patch_rcm(L0.A, P)) perm.insert(perm.end(), P[j].begin(), P[j].end());
+  // with coordinates the patches keep their construction order (Morton order
+  // of their seeds): a run of consecutive rows is then a compact region, and
+  // the tiles of the block SpMM gather few distinct rows; without coordinates
+  // reverse Cuthill-McKee keeps neighbouring patches close
+  std::vector<int> order;
+  if (!L0.coords.empty()) {
+    order.resize(P.size());
+    std::iota(order.begin(), order.end(), 0);
+  } else {
+    order = patch_rcm(L0.A, P);
+  }
+  for (int j : order) perm.insert(perm.end(), P[j].begin(), P[j].end());
   std::vector<int> iperm(n);
   for (int i = 0; i < n; ++i) iperm[perm[i]] = i;
   h.A_user = L0.A;
@@ -790,6 +801,66 @@ void upload_csr(const HostCSR& X, DBuf<int>& ptr, DBuf<int>& col, DBuf<double>& 
 }
 }  // namespace
 
+// Row-block tiling of the level-0 edge form for the LDS-staged block SpMM:
+// per block of kTileRows rows, the distinct rows of X its entries gather
+// (own rows first) and each entry's position in that list.  Left off when a
+// block exceeds kTileCols distinct columns or kTileNnz entries (orderings
+// without spatial locality), so the plain kernel runs instead.
+void build_tiles(const HostCSR& W, LevelDev& D, hipStream_t s) {
+  const int n = W.n_rows;
+  const int nblk = (n + kTileRows - 1) / kTileRows;
+  std::vector<std::vector<int>> urows(nblk);
+  std::vector<unsigned short> lcol(W.nnz());
+  std::vector<char> ok(nblk, 1);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int t = 0; t < nblk; ++t) {
+    const int r0 = t * kTileRows, r1 = std::min(n, r0 + kTileRows);
+    if (W.ptr[r1] - W.ptr[r0] > kTileNnz) {
+      ok[t] = 0;
+      continue;
+    }
+    std::vector<int> halo;
+    for (int64_t q = W.ptr[r0]; q < W.ptr[r1]; ++q)
+      if (W.col[q] < r0 || W.col[q] >= r1) halo.push_back(W.col[q]);
+    std::sort(halo.begin(), halo.end());
+    halo.erase(std::unique(halo.begin(), halo.end()), halo.end());
+    const int own = r1 - r0;
+    if (own + static_cast<int>(halo.size()) > kTileCols) {
+      ok[t] = 0;
+      continue;
+    }
+    std::vector<int>& u = urows[t];
+    for (int i = r0; i < r1; ++i) u.push_back(i);
+    u.insert(u.end(), halo.begin(), halo.end());
+    for (int64_t q = W.ptr[r0]; q < W.ptr[r1]; ++q) {
+      const int c = W.col[q];
+      const int pos = (c >= r0 && c < r1)
+                          ? c - r0
+                          : own + static_cast<int>(std::lower_bound(halo.begin(), halo.end(), c) -
+                                                   halo.begin());
+      lcol[q] = static_cast<unsigned short>(pos);
+    }
+  }
+  for (int t = 0; t < nblk; ++t)
+    if (!ok[t]) return;
+  std::vector<int> uptr(nblk + 1, 0), urow;
+  for (int t = 0; t < nblk; ++t) uptr[t + 1] = uptr[t] + static_cast<int>(urows[t].size());
+  urow.reserve(uptr[nblk]);
+  for (auto& u : urows) urow.insert(urow.end(), u.begin(), u.end());
+  D.t_uptr.upload(uptr, s);
+  D.t_urow.upload(urow, s);
+  D.t_lcol.upload(lcol, s);
+  D.A.t_uptr = D.t_uptr.p;
+  D.A.t_urow = D.t_urow.p;
+  D.A.t_lcol = D.t_lcol.p;
+  D.A.t_nblk = nblk;
+  MMD_HIP(hipStreamSynchronize(s));  // the host lists must outlive their copies
+  const char* e = std::getenv("MMDEIG_LOG");
+  if (e && std::atoi(e) != 0)
+    std::fprintf(stderr, "[mmd_build] level-0 tiles: %d blocks of %d rows, %.1f columns per block on average\n",
+                 nblk, kTileRows, static_cast<double>(uptr[nblk]) / nblk);
+}
+
 void upload_hierarchy(mmd_handle& h, hipStream_t s) {
   h.dev.clear();
   h.dev.resize(h.host.size());
@@ -819,6 +890,7 @@ void upload_hierarchy(mmd_handle& h, hipStream_t s) {
     D0.a_diag.upload(L0.s, s);
     D0.A.diag = D0.a_diag.p;
     D0.A.avg_row = static_cast<double>(L0.A.nnz()) / L0.n;
+    build_tiles(W, D0, s);
   }
   for (size_t k = 1; k < h.host.size(); ++k) {
     const LevelHost& L = h.host[k];

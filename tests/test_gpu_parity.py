@@ -110,6 +110,43 @@ def test_level_operators(built, torch_cuda):
             assert np.abs(Y - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("b", [33, 64, 130, 300])
+def test_level0_wide_apply_and_solve(built, torch_cuda, b):
+    """Level-0 block products wider than 32 columns: the LDS-tiled SpMM on the
+    graphs with coordinates (Morton row order), the row-per-wavefront kernel
+    on the grids; plain product and the fused CG form inside a block solve,
+    1, 2 and 5 column tiles with ragged last tiles."""
+    torch = torch_cuda
+    p, kw, dec, M = built
+    X = wl.random_block(p.n, b, seed=40 + b)
+    ref = krylov.EdgeForm(p.scipy()) @ X
+    Y = dec.apply(0, "A", _t(torch, X)).cpu().numpy()
+    assert np.abs(Y - ref).max() <= 1e-12 * np.abs(ref).max()
+    tol = 1e-10
+    Ad = p.scipy()
+    rhs = wl.random_block(p.n, b, seed=60 + b)
+    Xs, it = dec.solve(0, 0, _t(torch, rhs), tol=tol)
+    Xs = Xs.cpu().numpy()
+    nb = np.linalg.norm(rhs, axis=0)
+    floor = 50 * 2.2e-16 * float(abs(Ad).sum(axis=1).max()) * np.linalg.norm(Xs, axis=0) / nb
+    res = np.linalg.norm(rhs - Ad @ Xs, axis=0) / nb
+    assert np.all(res <= 1.5 * tol + floor)
+
+
+def test_level0_tiling_engaged(torch_cuda, capfd, monkeypatch):
+    """The tiled SpMM is what runs on a graph with coordinates."""
+    from paper_1804_03415_amd import Decomposition
+    monkeypatch.setenv("MMDEIG_LOG", "1")
+    p = wl.rgg(3000, 2)
+    dec = Decomposition.from_problem(p, levels=2)
+    err = capfd.readouterr().err
+    assert "level-0 tiles" in err
+    X = wl.random_block(p.n, 96, seed=5)
+    Y = dec.apply(0, "A", _t(torch_cuda, X)).cpu().numpy()
+    ref = krylov.EdgeForm(p.scipy()) @ X
+    assert np.abs(Y - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("b", [1, 4])
 def test_level_solves(built, torch_cuda, b):
     """b = 1 runs the persistent single-vector kernel, b = 4 the block kernels."""
