@@ -769,49 +769,55 @@ void pcg1_plan(const CsrView& A, const std::vector<int>& rp, Pcg1Plan& plan) {
   plan.resident = false;
   const int n = A.n_rows;
   if (n == 0 || (int)rp.size() != n + 1) return;
-  // 14 blocks per XCD measured best for the n = 1e5 RGG (barrier cost grows
-  // with the block count, the per-thread row count with fewer blocks)
-  int grid = 112;
-  if (const char* e = std::getenv("MMDEIG_RES_BLOCKS")) grid = std::max(8, std::atoi(e));
   if (const char* e = std::getenv("MMDEIG_NO_RESIDENT"))
     if (std::atoi(e) != 0) return;
-  grid = std::max(8, grid / 8 * 8);
-  grid = std::min(grid, std::max(8, (n + 63) / 64 / 8 * 8));
-  // balance nonzeros + rows: block j starts at the first row whose prefix
-  // weight reaches j / grid of the total
-  const double tot = static_cast<double>(rp[n]) + n;
-  std::vector<int> part(grid + 1, n);
-  part[0] = 0;
-  int i = 0;
-  for (int j = 1; j < grid; ++j) {
-    const double target = tot * j / grid;
-    while (i < n && static_cast<double>(rp[i]) + i < target) ++i;
-    part[j] = i;
-  }
-  size_t lds = 0;
-  int max_rows = 0;
-  const bool edge = A.diag != nullptr;
-  for (int j = 0; j < grid; ++j) {
-    const int nr = part[j + 1] - part[j];
-    const size_t ne = static_cast<size_t>(rp[part[j + 1]] - rp[part[j]]);
-    const size_t b = ne * 12 + (edge ? 8 * (size_t)nr : 0) + 4 * (size_t)(nr + 1);
-    lds = std::max(lds, b);
-    max_rows = std::max(max_rows, nr);
-  }
-  if (max_rows > kMaxU * kThreads) return;
+  // 14 blocks per XCD measured best for the n = 1e5 RGG (barrier cost grows
+  // with the block count, the per-thread row count with fewer blocks); a
+  // matrix whose slices do not fit that many blocks' LDS takes the fewest
+  // blocks (multiple of 8) that hold it, up to what can be co-resident
+  int grid0 = 112;
+  if (const char* e = std::getenv("MMDEIG_RES_BLOCKS")) grid0 = std::max(8, std::atoi(e));
+  grid0 = std::max(8, grid0 / 8 * 8);
+  grid0 = std::min(grid0, std::max(8, (n + 63) / 64 / 8 * 8));
   int dev = 0;
   MMD_HIP(hipGetDevice(&dev));
-  int maxsh = 0;
+  int maxsh = 0, cus = 0;
   MMD_HIP(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  MMD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   const size_t static_lds = sizeof(double) * (kThreads / kWave);
-  if (lds + static_lds > static_cast<size_t>(maxsh)) return;
+  const bool edge = A.diag != nullptr;
+  const double tot = static_cast<double>(rp[n]) + n;
+  std::vector<int> part;
+  size_t lds = 0;
+  int grid = grid0;
+  for (;; grid += 8) {
+    if (grid > cus) return;  // one 1024-thread block per CU at these LDS sizes
+    // balance nonzeros + rows: block j starts at the first row whose prefix
+    // weight reaches j / grid of the total
+    part.assign(grid + 1, n);
+    part[0] = 0;
+    int i = 0;
+    for (int j = 1; j < grid; ++j) {
+      const double target = tot * j / grid;
+      while (i < n && static_cast<double>(rp[i]) + i < target) ++i;
+      part[j] = i;
+    }
+    lds = 0;
+    int max_rows = 0;
+    for (int j = 0; j < grid; ++j) {
+      const int nr = part[j + 1] - part[j];
+      const size_t ne = static_cast<size_t>(rp[part[j + 1]] - rp[part[j]]);
+      const size_t b = ne * 12 + (edge ? 8 * (size_t)nr : 0) + 4 * (size_t)(nr + 1);
+      lds = std::max(lds, b);
+      max_rows = std::max(max_rows, nr);
+    }
+    if (max_rows <= kMaxU * kThreads && lds + static_lds <= static_cast<size_t>(maxsh)) break;
+  }
   lds = (lds + 255) / 256 * 256;
   MMD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cg1_res),
                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
   int per = 0;
   MMD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cg1_res, kThreads, lds));
-  int cus = 0;
-  MMD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   if (per <= 0 || grid > per * cus) return;
   plan.part.ensure(grid + 1);
   MMD_HIP(hipMemcpy(plan.part.p, part.data(), sizeof(int) * (grid + 1), hipMemcpyHostToDevice));
