@@ -170,7 +170,8 @@ def knn_backward(a):
     dec = Decomposition.from_problem(p, levels=a.levels, targets=(4, 8), exact_max_n=8000)
     t_build = time.perf_counter() - t
     print("knn-backward: build %.1f s" % t_build, file=sys.stderr, flush=True)
-    lam, V, stats, el_f = timed_solves(dec, argparse.Namespace(nev=nev, tol=a.tol), "fp64",
+    fwd = argparse.Namespace(nev=nev, tol=a.tol, alpha=a.alpha, beta=a.beta)
+    lam, V, stats, el_f = timed_solves(dec, fwd, "fp64",
                                        a.steps, a.warmup)
     x = torch.from_numpy(p.coords[:, 0]).cuda()
     gl = np.ones(nev)
