@@ -170,7 +170,10 @@ void gram(const double* X, int ldx, const double* Y, int ldy, int n, int m, int 
 // Z (n x p, ldz) = alpha * X (n x m, ldx) * C (m x p, ldc, device) + beta * Z
 void gemm_nn(const double* X, int ldx, const double* C, int ldc, double* Z, int ldz, int n,
              int m, int p, double alpha, double beta, hipStream_t s);
-// matrix-vector forms for one column (Lanczos): h[m] = X^T y ; z -= X h
+// matrix-vector forms for one column (Lanczos): h[m] = X^T y ; z -= X h.
+// gemv_t splits the rows into at most kGemvChunks chunks; work holds
+// kGemvChunks x m doubles.
+constexpr int kGemvChunks = 1024;
 void gemv_t(const double* X, int ldx, const double* y, int n, int m, double* h,
             double* work, hipStream_t s);
 void gemv_n_sub(const double* X, int ldx, const double* h, int n, int m, double* z,

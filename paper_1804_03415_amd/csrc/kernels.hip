@@ -1101,14 +1101,24 @@ __global__ __launch_bounds__(kBlock) void k_gemm_nn(const double* __restrict__ X
     }
 }
 
-__global__ void k_gemv_t(const double* __restrict__ X, int ldx, const double* __restrict__ y,
-                         int n, int m, int chunk, double* __restrict__ work) {
+// thread c of a block sums its column over one chunk of rows, four rows per
+// pass with separate accumulators so four loads are in flight
+__global__ __launch_bounds__(kBlock) void k_gemv_t(const double* __restrict__ X, int ldx,
+                                                   const double* __restrict__ y, int n, int m,
+                                                   int chunk, double* __restrict__ work) {
   const int c = blockIdx.y * blockDim.x + threadIdx.x;
   if (c >= m) return;
   const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
-  double acc = 0.0;
-  for (int i = lo; i < hi; ++i) acc += X[(size_t)i * ldx + c] * y[i];
-  work[(size_t)blockIdx.x * m + c] = acc;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int i = lo;
+  for (; i + 3 < hi; i += 4) {
+    a0 += X[(size_t)i * ldx + c] * y[i];
+    a1 += X[(size_t)(i + 1) * ldx + c] * y[i + 1];
+    a2 += X[(size_t)(i + 2) * ldx + c] * y[i + 2];
+    a3 += X[(size_t)(i + 3) * ldx + c] * y[i + 3];
+  }
+  for (; i < hi; ++i) a0 += X[(size_t)i * ldx + c] * y[i];
+  work[(size_t)blockIdx.x * m + c] = (a0 + a1) + (a2 + a3);
 }
 
 __global__ __launch_bounds__(kBlock) void k_gemv_n_sub(const double* __restrict__ X, int ldx,
@@ -1422,10 +1432,11 @@ void gemm_nn(const double* X, int ldx, const double* C, int ldc, double* Z, int 
 void gemv_t(const double* X, int ldx, const double* y, int n, int m, double* h, double* work,
             hipStream_t s) {
   if (m == 0) return;
-  const int chunk = std::max(64, ceil_div(n, 256));
+  const int chunk = std::max(32, ceil_div(n, kGemvChunks));
   const int nch = ceil_div(n, chunk);
-  hipLaunchKernelGGL(k_gemv_t, dim3(nch, ceil_div(m, kBlock)), dim3(kBlock), 0, s, X, ldx, y, n,
-                     m, chunk, work);
+  const int threads = std::min(kBlock, ceil_div(m, kWave) * kWave);
+  hipLaunchKernelGGL(k_gemv_t, dim3(nch, ceil_div(m, threads)), dim3(threads), 0, s, X, ldx, y,
+                     n, m, chunk, work);
   check_launch();
   reduce_partials(work, nch, m, h, s);
 }

@@ -781,7 +781,7 @@ void Solver::lanczos_orth(Lanczos& L, double* w, int jcols, std::vector<double>*
   double* y = L.y;
   double* h1 = pool_.d("lz:h1", std::max(L.mi, 1));
   double* h2 = pool_.d("lz:h2", std::max(jcols, 1));
-  double* work = pool_.d("lz:gw", (size_t)256 * std::max(std::max(L.mi, jcols), 1));
+  double* work = pool_.d("lz:gw", (size_t)kGemvChunks * std::max(std::max(L.mi, jcols), 1));
   double last = 0.0;
   for (int pass = 0; pass < 2; ++pass) {
     if (L.k == 0) copy_block(w, 1, y, 1, n, 1, s_);
