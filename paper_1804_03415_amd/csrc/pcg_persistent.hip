@@ -74,9 +74,18 @@ __device__ inline double grid_sum(Ctx& c, double part, double* sh) {
   double* r = c.red + (size_t)c.slot * 2 * c.nblk;  // slot regions are disjoint
   if (threadIdx.x == 0) r[c.blk] = b;
   grid_barrier(c);
-  double t = 0.0;
-  for (int j = threadIdx.x; j < c.nblk; j += kThreads) t += r[j];
-  const double s = block_sum(t, sh);
+  // the first wavefront adds the partials (same order in every block) and
+  // hands the sum to the others through LDS: one block barrier instead of a
+  // full block reduction
+  if (threadIdx.x < kWave) {
+    double t = 0.0;
+    for (int j = threadIdx.x; j < c.nblk; j += kWave) t += r[j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, kWave);
+    if (threadIdx.x == 0) sh[0] = t;
+  }
+  __syncthreads();
+  const double s = sh[0];
   c.slot ^= 1;
   return s;
 }
@@ -92,13 +101,25 @@ __device__ inline void grid_sum2(Ctx& c, double p1, double p2, double* sh, doubl
     r[c.nblk + c.blk] = b2;
   }
   grid_barrier(c);
-  double t1 = 0.0, t2 = 0.0;
-  for (int j = threadIdx.x; j < c.nblk; j += kThreads) {
-    t1 += r[j];
-    t2 += r[c.nblk + j];
+  if (threadIdx.x < kWave) {
+    double t1 = 0.0, t2 = 0.0;
+    for (int j = threadIdx.x; j < c.nblk; j += kWave) {
+      t1 += r[j];
+      t2 += r[c.nblk + j];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      t1 += __shfl_xor(t1, off, kWave);
+      t2 += __shfl_xor(t2, off, kWave);
+    }
+    if (threadIdx.x == 0) {
+      sh[0] = t1;
+      sh[1] = t2;
+    }
   }
-  s1 = block_sum(t1, sh);
-  s2 = block_sum(t2, sh);
+  __syncthreads();
+  s1 = sh[0];
+  s2 = sh[1];
   c.slot ^= 1;
 }
 
