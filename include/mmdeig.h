@@ -85,7 +85,15 @@ typedef struct {
   int32_t max_refine;      /* refinement iterations per level [200]              */
   int32_t streams;         /* eig_leftmost_batched: problems solved concurrently,
                               one HIP stream and host thread each [8]           */
-  int32_t reserved;
+  int32_t stop_level;      /* 0: solve down to level 0 [0].  k in 1..K: the
+                              coarse-level approximation of Section 7.3 --
+                              Alg. 6 (as printed it stops at level 1) stopped
+                              after level k, returning lambda = 1/mu of the
+                              level-k pairs and v = Psi^(1)...Psi^(k) z, within
+                              eps_k of the true pairs (Lemma 3.3); tol is not
+                              used                                             */
+  int32_t d;               /* extension block size of every level (0: the
+                              default max(1, min(N^(k)/10, nev/10)))            */
 } eig_opts;
 
 #define MMD_MAX_LEVELS 16
@@ -200,8 +208,10 @@ int eig_backward(mmd_handle* h, int32_t nev, const double* evals, const double* 
  * leading dimension b).  op: 0 = A^(k) (N^(k) -> N^(k)), 1 = M^(k),
  * 2 = B^(k+1) = U^T A^(k) U (reduced -> reduced, needs k < K),
  * 3 = U^(k+1) (reduced -> N^(k)), 4 = U^(k+1)^T (N^(k) -> reduced),
- * 5 = Psi^(k+1) (N^(k+1) -> N^(k)).  Level 0 A is applied in edge form
- * y_i = s_i x_i + sum_j w_ij (x_i - x_j) (Section 2.1 elements). */
+ * 5 = Psi^(k+1) (N^(k+1) -> N^(k)), 6 = A^(0) in FP32 arithmetic (level 0
+ * only: X rounded to FP32, the FP32 matrix copy and kernel of the
+ * mixed-precision solves, the result widened to FP64).  Level 0 A is applied
+ * in edge form y_i = s_i x_i + sum_j w_ij (x_i - x_j) (Section 2.1 elements). */
 int mmd_apply(mmd_handle* h, int32_t level, int32_t op, const double* X, double* Y,
               int32_t b, void* hip_stream);
 

@@ -56,3 +56,30 @@ def component_count(A):
     G.setdiag(0)
     G.eliminate_zeros()
     return connected_components(G, directed=False)[0]
+
+
+def shift_cluster(A):
+    """Smallest eigenvalue of each connected component of a stored graph
+    operator A = L + diag(s) (Section 2.1 energy form), ascending.
+
+    On a component C the indicator vector 1_C is an exact eigenvector of the
+    exact-arithmetic matrix when every row sum s_i equals the same shift; the
+    stored FP64 diagonal a_ii = sum_j w_ij + s_i is rounded, so the stored
+    matrix's row sums deviate by up to u ||A||_inf.  Its eigenvalue nearest the
+    shift is then the Rayleigh quotient of 1_C, the mean row sum over C (each
+    row summed exactly with math.fsum), up to a second-order term (spread of
+    the row sums over C)^2 / (spectral gap of C).  This is the reference value
+    of the shift cluster of a graph Laplacian plus a shift.
+    """
+    import math
+    from scipy.sparse.csgraph import connected_components
+    A = sp.csr_matrix(A)
+    G = A.copy()
+    G.setdiag(0)
+    G.eliminate_zeros()
+    nc, lab = connected_components(G, directed=False)
+    rs = np.array([math.fsum(A.data[A.indptr[i]:A.indptr[i + 1]]) for i in range(A.shape[0])])
+    out = np.empty(nc)
+    for c in range(nc):
+        out[c] = math.fsum(rs[lab == c]) / np.count_nonzero(lab == c)
+    return np.sort(out)

@@ -25,7 +25,9 @@ design notes):
     efficiency condition (ii) of Section 5 with the current Ritz values:
     mu_ml <= gamma mu_mh, gamma = (1 + beta) / alpha, so guard columns remain.
   * Alg. 6 is continued down to level 0 (A^(0) = A, M^(0) = I), then a final
-    inverse-iteration + Rayleigh-Ritz step with A gives the output pairs.
+    inverse-iteration + Rayleigh-Ritz step with A gives the output pairs; it
+    is repeated while a returned pair's relative residual exceeds 10 tol
+    (until that residual stagnates).
   * Single-vector Lanczos cannot see a second copy of an exactly degenerate
     eigenvalue; level 0 ends with a multiplicity check (fresh random start
     deflated against the accepted pairs) that swaps in any missed pair.
@@ -517,26 +519,56 @@ def canonical_sign(V):
     return V
 
 
-def final_pairs(A, V, D, nev, tol, st):
+def final_pairs(A, V, D, nev, tol, st, max_passes=30):
     """Output step on level 0: F = A^-1 V (CG from mu_i v_i), orthonormalise, Rayleigh-Ritz with A.
 
-    A is the level-0 operator in edge form.
+    A is the level-0 operator in edge form.  The step is repeated (block
+    inverse iteration on the Ritz block) while a returned pair misses the
+    relative residual ||A v - lambda v|| / (lambda ||v||) <= 10 tol, until the
+    largest such residual stops falling by 10% per pass or max_passes is
+    reached (reading of the output accuracy, see the module notes).
     """
-    F = np.zeros_like(V)
-    for i in range(V.shape[1]):
-        F[:, i] = pcg(lambda x: A @ x, V[:, i], None, D[i] * V[:, i], tol, st)
-    Q = mqr(F, None)
-    H = Q.T @ (A @ Q)
-    lam, Y = np.linalg.eigh(0.5 * (H + H.T))
-    Vout = Q @ Y[:, :nev]
+    prev = np.inf
+    for _ in range(max_passes):
+        F = np.zeros_like(V)
+        for i in range(V.shape[1]):
+            F[:, i] = pcg(lambda x: A @ x, V[:, i], None, D[i] * V[:, i], tol, st)
+        Q = mqr(F, None)
+        H = Q.T @ (A @ Q)
+        lam, Y = np.linalg.eigh(0.5 * (H + H.T))
+        Vall = Q @ Y
+        R = A @ Vall[:, :nev] - Vall[:, :nev] * lam[None, :nev]
+        rho = np.linalg.norm(R, axis=0) / (np.abs(lam[:nev]) * np.linalg.norm(Vall[:, :nev], axis=0))
+        worst = float(rho.max())
+        if worst <= 10.0 * tol or worst > 0.9 * prev:
+            break
+        prev = worst
+        V, D = Vall, 1.0 / lam
+    Vout = Vall[:, :nev]
     Vout /= np.linalg.norm(Vout, axis=0)[None, :]
     return lam[:nev], canonical_sign(Vout)
 
 
+def coarse_pairs(mmd: MMD, k: int, V, D, nev):
+    """Coarse-level approximation (Section 7.3): the level-k pairs z_i with
+    mu_i = 1 / lambda_i, lifted as v_i = Psi^(1) ... Psi^(k) z_i.  With z
+    M^(k)-orthonormal the v_i are orthonormal (M^(k) is the Gram matrix of the
+    composite basis); |mu_i - mu_i(A^-1)| <= eps_k by Lemma 3.3."""
+    if V.shape[1] < nev:
+        raise NotConverged("coarse-level approximation: fewer pairs than nev on level %d" % k)
+    Z = V[:, :nev]
+    for j in range(k, 0, -1):
+        Z = mmd.levels[j].Psi @ Z
+    Z = Z / np.linalg.norm(Z, axis=0)[None, :]
+    return 1.0 / D[:nev], canonical_sign(Z)
+
+
 def eig_leftmost(A, nev, tol, mmd: Optional[MMD] = None, alpha=3.0, beta=1.0, c=1,
-                 seed=0, mmd_kwargs=None, return_stats=False):
+                 seed=0, mmd_kwargs=None, return_stats=False, stop_level=0):
     """The nev smallest eigenpairs of the SPD matrix A by Alg. 6 (continued to level 0).
 
+    stop_level k >= 1 stops Alg. 6 after level k (the printed algorithm stops
+    at level 1) and returns the coarse-level approximation of that level.
     Returns (lambda ascending [nev], V [n, nev]) and, optionally, Stats.
     """
     A = sp.csr_matrix(A)
@@ -549,24 +581,41 @@ def eig_leftmost(A, nev, tol, mmd: Optional[MMD] = None, alpha=3.0, beta=1.0, c=
     stats = Stats()
     E0 = EdgeForm(A)
     K = mmd.K
+    if not 0 <= stop_level <= K:
+        raise ValueError("stop_level must lie between 0 and K")
     if K == 0:
         V = np.zeros((n, 0))
         D = np.zeros(0)
     else:
-        V, D = coarsest(mmd, sch.mu_ex[K], nev)
+        # on the coarsest level itself the approximation keeps the nev leading
+        # pairs of the dense problem, without the exploration threshold
+        V, D = coarsest(mmd, sch.mu_ex[K] if stop_level < K else 0.0, nev)
         stats.lev(K)["ext_out"] = V.shape[1]
-    for k in range(K - 1, -1, -1):
+    for k in range(K - 1, stop_level - 1, -1):
         # the PCG of OP and of the refinement stops at a relative residual
         # eps^(k); without the paper's scaling (lambda_1 = 1) eps^(k) = 0.1 eps_k
         # can exceed 1, where x = 0 already passes and OP vanishes: the
         # relative tolerance on levels k >= 1 is min(eps^(k), 0.1)
         t_pcg = 0.1 * sch.eps_op[k] if k == 0 else min(0.1, sch.eps_op[k])
+        if k == stop_level and k > 0 and D.size:
+            # the returned level: OP accurate to eps^(k) in mu units, i.e.
+            # relative eps^(k) / mu_1 (mu_1 = 1 under the paper's scaling)
+            t_pcg = min(0.1, sch.eps_op[k] / float(D[0]))
         ops = LevelOps(mmd, k, sch.eps_op[k] if k == 0 else t_pcg, stats, E0)
         V = mmd.levels[k + 1].Psi @ V
         V, D = refine(ops, V, D, sch.eps_op[k], sch.mu_re[k], mmd.levels[k].lam_max_M,
                       gamma=(1.0 + beta) / alpha, eps_solve=t_pcg)
         V, D = extend(ops, V, D, nev, sch.eps_op[k], sch.mu_ex[k], sch.d[k], c,
                       relative=(k == 0), seed=seed)
+    if stop_level > 0:
+        if stop_level < K:
+            # missed copies of repeated eigenvalues, as on level 0 (absolute test in mu)
+            V, D = multiplicity_check(ops, V, D, sch.eps_op[stop_level], sch.d[stop_level], c,
+                                      relative=False, seed=seed)
+        lam, Vout = coarse_pairs(mmd, stop_level, V, D, nev)
+        if return_stats:
+            return lam, Vout, stats
+        return lam, Vout
     if K == 0:
         ops = LevelOps(mmd, 0, tol, stats, E0)
         V, D = extend(ops, V, D, nev, tol, 0.0, sch.d[0], c, relative=True, seed=seed)

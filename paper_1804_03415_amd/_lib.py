@@ -44,7 +44,8 @@ class eig_opts(ctypes.Structure):
                 ("restart_mult", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("max_restarts", ctypes.c_int32),
                 ("max_refine", ctypes.c_int32),
-                ("streams", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("streams", ctypes.c_int32), ("stop_level", ctypes.c_int32),
+                ("d", ctypes.c_int32)]
 
 
 _L = MMD_MAX_LEVELS
@@ -131,7 +132,13 @@ def _ptr(a):
 
 
 def _stream(stream):
+    """The HIP stream handle of a torch stream (default: torch's current one).
+    Without a visible device this is NULL, the HIP default stream: input
+    checks that precede device work still report their status, and the first
+    device call fails with MMD_EHIP."""
     import torch
     if stream is None:
+        if not torch.cuda.is_available():
+            return None
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream)

@@ -3,14 +3,26 @@
 Device buffers are torch tensors on the current HIP device; all work is
 enqueued on the current torch stream.  Functions mirror include/mmdeig.h.
 """
+import atexit
 import ctypes
+import weakref
 
 import numpy as np
 
 from . import _lib
 from ._lib import MMDError, check, eig_opts, eig_stats, lib, mmd_build_opts, mmd_csr
 
-OPS = {"A": 0, "M": 1, "B": 2, "U": 3, "Ut": 4, "Psi": 5}
+OPS = {"A": 0, "M": 1, "B": 2, "U": 3, "Ut": 4, "Psi": 5, "A32": 6}
+
+# every open handle, so they can all be released while the HIP runtime is
+# still fully alive (at interpreter exit, before native exit handlers run)
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for d in list(_LIVE):
+        d.close()
 
 
 def build_options(levels=3, targets=(4, 8), grid_blocks=(4, 2), r_hops=1, exact_max_n=0,
@@ -30,10 +42,13 @@ def build_options(levels=3, targets=(4, 8), grid_blocks=(4, 2), r_hops=1, exact_
 
 
 def solver_options(alpha=3.0, beta=1.0, restart_mult=1, seed=0, max_restarts=2000,
-                   max_refine=200, precision="fp64", streams=8):
+                   max_refine=200, precision="fp64", streams=8, stop_level=0, d=0):
     """eig_opts; precision "fp64" or "fp32-refine" (FP32 CG inside FP64
-    iterative refinement for the level-0 block solves)."""
+    iterative refinement for the level-0 block solves); stop_level k >= 1
+    returns the coarse-level approximation of level k; d the extension block
+    size (0: default)."""
     o = eig_opts()
+    o.stop_level, o.d = stop_level, d
     o.alpha, o.beta, o.restart_mult, o.seed = alpha, beta, restart_mult, seed
     o.max_restarts, o.max_refine = max_restarts, max_refine
     if precision not in ("fp64", "fp32-refine"):
@@ -71,19 +86,29 @@ class Decomposition:
         self._L = lib()
         self.n = n
         self.nnz = int(rowptr[-1])
+        _LIVE.add(self)
 
     @classmethod
     def from_problem(cls, p, **opts):
         return cls(p.rowptr, p.col, p.val, coords=None if p.grid else p.coords, grid=p.grid, **opts)
 
-    def __del__(self):
-        # the library object is held by the instance, so freeing works also
-        # while the interpreter tears module globals down
+    def close(self):
+        """Release the handle and its device memory now (mmd_free); idempotent."""
         h = getattr(self, "h", None)
         L = getattr(self, "_L", None)
         if h is not None and h.value and L is not None:
             L.mmd_free(h)
-            self.h = None
+        self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
+    def __del__(self):
+        self.close()
 
     def info(self):
         K = ctypes.c_int32()
@@ -122,7 +147,7 @@ class Decomposition:
 
     def _out_rows(self, level, op):
         s = self.info()["sizes"]
-        if op in (0, 1, 3, 5):
+        if op in (0, 1, 3, 5, 6):
             return s[level]
         return s[level] - s[level + 1]  # B and U^T map into the reduced space
 
@@ -253,3 +278,4 @@ def spmm(rowptr, col, val, X, n_cols=None, stream=None):
     check(lib().mmdk_spmm(n_rows, n_cols, _lib._ptr(rowptr), _lib._ptr(col), _lib._ptr(val),
                           _lib._ptr(X), _lib._ptr(Y), b, _lib._stream(stream)))
     return Y
+

@@ -140,9 +140,11 @@ void gather_scalars(ColScalars src, ColScalars dst, const int* idx, int m, hipSt
 // column-major output: out[c*n + perm[i]] = X[i*ldx + c] * colscale[c] (perm may be null)
 void to_colmajor(const double* X, int ldx, const double* colscale, double* out, int n, int b,
                  const int* perm, hipStream_t s);
-// per column: the entry of largest |X(i,c)| (ties: lowest perm[i], or i when perm is null)
+// per column: the entry of largest |X(i,c)| (ties: lowest perm[i], or i when perm is null);
+// work_idx / work_val hold col_absmax_work_size(n, b) entries each
+size_t col_absmax_work_size(int n, int b);
 void col_absmax(const double* X, int ldx, int n, int b, int* idx, double* val,
-                const int* perm, hipStream_t s);
+                const int* perm, int* work_idx, double* work_val, hipStream_t s);
 // rows: gather Y[i] = X[idx[i]] or scatter Y[idx[i]] = X[i] (n rows, b columns)
 void permute_rows(const double* X, int ldx, double* Y, int ldy, int n, int b, const int* idx,
                   bool scatter, hipStream_t s);

@@ -1374,20 +1374,23 @@ void permute_rows(const double* X, int ldx, double* Y, int ldy, int n, int b, co
   check_launch();
 }
 
-void col_absmax(const double* X, int ldx, int n, int b, int* idx, double* val, const int* perm,
-                hipStream_t s) {
-  // partial results live in the tail of the output-sized scratch the caller owns
-  static thread_local DBuf<int> pidx;
-  static thread_local DBuf<double> pval;
+static int absmax_chunks(int n) {
   const int chunk = std::max(256, ceil_div(n, 256));
-  const int nch = ceil_div(n, chunk);
-  pidx.ensure((size_t)nch * b);
-  pval.ensure((size_t)nch * b);
+  return std::max(1, ceil_div(n, chunk));
+}
+
+size_t col_absmax_work_size(int n, int b) { return (size_t)absmax_chunks(n) * b; }
+
+void col_absmax(const double* X, int ldx, int n, int b, int* idx, double* val, const int* perm,
+                int* work_idx, double* work_val, hipStream_t s) {
+  // per-chunk candidates go to the caller's work arrays (col_absmax_work_size each)
+  const int chunk = std::max(256, ceil_div(n, 256));
+  const int nch = absmax_chunks(n);
   hipLaunchKernelGGL(k_absmax_part, dim3(nch, ceil_div(b, kBlock)), dim3(kBlock), 0, s, X, ldx,
-                     n, b, chunk, pidx.p, pval.p, perm);
+                     n, b, chunk, work_idx, work_val, perm);
   check_launch();
-  hipLaunchKernelGGL(k_absmax_fin, dim3(ceil_div(b, kBlock)), dim3(kBlock), 0, s, pidx.p,
-                     pval.p, nch, b, idx, val);
+  hipLaunchKernelGGL(k_absmax_fin, dim3(ceil_div(b, kBlock)), dim3(kBlock), 0, s, work_idx,
+                     work_val, nch, b, idx, val);
   check_launch();
 }
 

@@ -44,8 +44,10 @@ __device__ inline void grid_barrier(Ctx& c) {
   c.gen += 1;
   if (threadIdx.x == 0) {
     __hip_atomic_fetch_add(c.bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    // modular comparison: the counter may wrap past 2^32 in a long solve, the
+    // distance to the target never exceeds gridDim.x
     const unsigned target = c.gen * (unsigned)gridDim.x;
-    while (__hip_atomic_load(c.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target)
+    while ((int)(__hip_atomic_load(c.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0)
       __builtin_amdgcn_s_sleep(1);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }

@@ -1011,8 +1011,11 @@ void Solver::extend(int k, double*& V, std::vector<double>& D, int& m, int m_tar
   if (st_) st_->ext_out[k] += mo;
 }
 
-void Solver::multiplicity_check(double*& V, std::vector<double>& D, int m, double eps, int d) {
-  const int n = nlev(0);
+void Solver::multiplicity_check(int k, double*& V, std::vector<double>& D, int m, double eps,
+                                int d) {
+  // level 0: relative tests (eps * theta); coarse levels: absolute in mu
+  const bool relative = k == 0;
+  const int n = nlev(k);
   const int cap = n - m;
   if (cap <= 0 || m == 0) return;
   const int c = o_.restart_mult;
@@ -1020,15 +1023,15 @@ void Solver::multiplicity_check(double*& V, std::vector<double>& D, int m, doubl
     const int s = std::min(d + 10, cap);
     const int p = std::min(c * d, cap - 1);
     Lanczos L;
-    L.eps_op = eps;
-    lanczos_init(L, 0, V, m, std::max(s, 1 + p));
+    L.eps_op = k == 0 ? eps : tpcg_[k];
+    lanczos_init(L, k, V, m, std::max(s, 1 + p));
     lanczos_steps(L, s);
     std::vector<double> dd, ee, th;
     tri_of(L.T, L.cap, L.j, dd, ee);
     dense::tridiag_eig(L.j, dd.data(), ee.data(), th, nullptr, 0);
-    const double lim = D[m - 1] * (1.0 + eps);
+    const double lim = relative ? D[m - 1] * (1.0 + eps) : D[m - 1] + eps;
     if (th.back() <= lim) return;
-    while (p > 0 && !ritz_converged(L, 1, eps, true)) {
+    while (p > 0 && !ritz_converged(L, 1, eps, relative)) {
       restart(L, 1, L.j - 1);
       lanczos_steps(L, p);
     }
@@ -1226,7 +1229,7 @@ void Solver::refine(int k, double*& V, std::vector<double>& D, int& m, double ep
 }
 
 // ------------------------------------------------------------------ output step
-void Solver::final_pairs(double* V, const std::vector<double>& D, int m, int nev, double tol,
+void Solver::final_pairs(double* V, const std::vector<double>& D0, int m, int nev, double tol,
                          double* evals, double* evecs) {
   const int n = nlev(0);
   MMD_REQUIRE(m >= nev, MMD_ENOCONV, "fewer converged pairs than requested");
@@ -1234,47 +1237,111 @@ void Solver::final_pairs(double* V, const std::vector<double>& D, int m, int nev
   double* Dd = pool_.d("fp:D", m);
   double* AQ = pool_.d("fp:AQ", (size_t)n * m);
   double* Hd = pool_.d("fp:H", (size_t)m * m);
-  double* Yd = pool_.d("fp:Y", (size_t)m * nev);
-  double* Vo = pool_.d("fp:V", (size_t)n * nev);
+  double* Yd = pool_.d("fp:Y", (size_t)m * m);
+  double* Vo = pool_.d("fp:V", (size_t)n * m);
+  double* Rr = pool_.d("fp:Rr", (size_t)n * nev);
   double* work = pool_.d("gram:w", gram_work_size(n, m, m));
-  h2d(Dd, D.data(), m);
-  scale_cols(V, m, Dd, F, m, n, m, false, s_);
-  std::vector<int> its;
-  cg(0, OpKind::A, V, m, F, m, n, m, tol, true, nullptr, 0, "cg0", st_ ? &its : nullptr);
-  if (st_) {
-    st_->pcg_A_calls[0] += m;
-    for (int x : its) st_->pcg_A_iters[0] += x;
+  double* pr = pool_.d("fp:pr", (size_t)kRedBlocks * m);
+  double* cn = pool_.d("fp:cn", m);
+  double* ld = pool_.d("fp:ld", m);
+  std::vector<double> D(D0.begin(), D0.begin() + m), lam, Z;
+  // Inverse iteration + Rayleigh-Ritz with A on the block, repeated while a
+  // returned pair misses ||A v - lambda v|| <= 10 tol lambda ||v|| and the
+  // largest such residual still falls by 10% per pass.
+  const int max_passes = 30;
+  double prev = std::numeric_limits<double>::infinity();
+  for (int pass = 0;; ++pass) {
+    h2d(Dd, D.data(), m);
+    scale_cols(V, m, Dd, F, m, n, m, false, s_);
+    std::vector<int> its;
+    cg(0, OpKind::A, V, m, F, m, n, m, tol, true, nullptr, 0, "cg0", st_ ? &its : nullptr);
+    if (st_) {
+      st_->pcg_A_calls[0] += m;
+      for (int x : its) st_->pcg_A_iters[0] += x;
+    }
+    mqr(0, F, n, m, "fq");
+    applyA(0, F, m, AQ, m, m);
+    gram(F, m, AQ, m, n, m, m, Hd, m, work, s_);
+    std::vector<double> Hh((size_t)m * m);
+    d2h(Hh.data(), Hd, Hh.size());
+    sync();
+    dense::sym_eig(m, Hh.data(), lam, &Z);
+    h2d(Yd, Z.data(), Z.size());
+    gemm_nn(F, m, Yd, m, Vo, m, n, m, m, 1.0, 0.0, s_);
+    // residual norms of the nev returned pairs: R = A V - V diag(lambda)
+    h2d(ld, lam.data(), nev);
+    applyA(0, Vo, m, Rr, nev, nev);
+    double* Tv = AQ;  // free again: V diag(lambda) for the nev columns
+    scale_cols(Vo, m, ld, Tv, nev, n, nev, false, s_);
+    axpby(-1.0, Tv, nev, 1.0, Rr, nev, n, nev, s_);
+    int nb = col_dot(Rr, nev, Rr, nev, n, nev, pr, s_);
+    reduce_partials(pr, nb, nev, cn, s_);
+    nb = col_dot(Vo, m, Vo, m, n, nev, pr, s_);
+    reduce_partials(pr, nb, nev, ld, s_);
+    std::vector<double> rn(nev), vn(nev);
+    d2h(rn.data(), cn, nev);
+    d2h(vn.data(), ld, nev);
+    sync();
+    double worst = 0.0;
+    for (int j = 0; j < nev; ++j)
+      worst = std::max(worst, std::sqrt(rn[j]) / (std::fabs(lam[j]) * std::sqrt(vn[j])));
+    if (log_on())
+      std::fprintf(stderr, "[mmdeig] output pass %d: max relative residual %.3e\n", pass, worst);
+    if (worst <= 10.0 * tol || worst > 0.9 * prev || pass + 1 >= max_passes) break;
+    prev = worst;
+    // next pass: the Ritz block (all m columns) and its mu = 1 / lambda
+    copy_block(Vo, m, V, m, n, m, s_);
+    for (int j = 0; j < m; ++j) D[j] = 1.0 / lam[j];
   }
-  mqr(0, F, n, m, "fq");
-  applyA(0, F, m, AQ, m, m);
-  gram(F, m, AQ, m, n, m, m, Hd, m, work, s_);
-  std::vector<double> Hh((size_t)m * m), lam, Z;
-  d2h(Hh.data(), Hd, Hh.size());
-  sync();
-  dense::sym_eig(m, Hh.data(), lam, &Z);
-  std::vector<double> Yh((size_t)m * nev);
-  for (int i = 0; i < m; ++i)
-    for (int j = 0; j < nev; ++j) Yh[(size_t)i * nev + j] = Z[(size_t)i * m + j];
-  h2d(Yd, Yh.data(), Yh.size());
-  gemm_nn(F, m, Yd, nev, Vo, nev, n, m, nev, 1.0, 0.0, s_);
-  double* pr = pool_.d("fp:pr", (size_t)kRedBlocks * nev);
-  double* cn = pool_.d("fp:cn", nev);
-  int* ai = pool_.i("fp:ai", nev);
-  double* av = pool_.d("fp:av", nev);
-  const int nb = col_dot(Vo, nev, Vo, nev, n, nev, pr, s_);
+  double* Vn = pool_.d("fp:Vn", (size_t)n * nev);
+  copy_block(Vo, m, Vn, nev, n, nev, s_);
+  emit_pairs(Vn, lam, nev, evals, evecs);
+}
+
+void Solver::emit_pairs(const double* Vn, const std::vector<double>& lam, int nev, double* evals,
+                        double* evecs) {
+  // unit 2-norm, largest-magnitude entry positive (lowest caller index on
+  // ties), column-major in the caller's numbering
+  const int n = nlev(0);
+  double* pr = pool_.d("ep:pr", (size_t)kRedBlocks * nev);
+  double* cn = pool_.d("ep:cn", nev);
+  int* ai = pool_.i("ep:ai", nev);
+  double* av = pool_.d("ep:av", nev);
+  const int nb = col_dot(Vn, nev, Vn, nev, n, nev, pr, s_);
   reduce_partials(pr, nb, nev, cn, s_);
   const int* perm = h_.perm.empty() ? nullptr : h_.d_perm.p;
-  col_absmax(Vo, nev, n, nev, ai, av, perm, s_);
+  const size_t aw = col_absmax_work_size(n, nev);
+  col_absmax(Vn, nev, n, nev, ai, av, perm, pool_.i("ep:awi", aw), pool_.d("ep:awv", aw), s_);
   std::vector<double> nrm(nev), amax(nev), scale(nev);
   d2h(nrm.data(), cn, nev);
   d2h(amax.data(), av, nev);
   sync();
   for (int j = 0; j < nev; ++j) scale[j] = (amax[j] < 0 ? -1.0 : 1.0) / std::sqrt(nrm[j]);
-  double* sd = pool_.d("fp:sc", nev);
+  double* sd = pool_.d("ep:sc", nev);
   h2d(sd, scale.data(), nev);
-  to_colmajor(Vo, nev, sd, evecs, n, nev, perm, s_);
+  to_colmajor(Vn, nev, sd, evecs, n, nev, perm, s_);
   for (int j = 0; j < nev; ++j) evals[j] = lam[j];
   sync();
+}
+
+void Solver::coarse_output(const double* V, const std::vector<double>& D, int m, int k, int nev,
+                           double* evals, double* evecs) {
+  // Section 7.3: lambda = 1 / mu of the level-k pairs, v = Psi^(1) ... Psi^(k) z
+  MMD_REQUIRE(m >= nev, MMD_ENOCONV,
+              "coarse-level approximation: level " + std::to_string(k) + " produced " +
+                  std::to_string(m) + " pairs, fewer than nev");
+  const double* cur = V;
+  int ld = m;
+  for (int j = k; j >= 1; --j) {
+    const int nf = nlev(j - 1);
+    double* nxt = pool_.d(j % 2 ? "co:a" : "co:b", (size_t)nf * nev);
+    spmm(h_.dev[j].Psi, cur, ld, nxt, nev, nev, s_);
+    cur = nxt;
+    ld = nev;
+  }
+  std::vector<double> lam(nev);
+  for (int j = 0; j < nev; ++j) lam[j] = 1.0 / D[j];
+  emit_pairs(cur, lam, nev, evals, evecs);
 }
 
 // ------------------------------------------------------------------ driver (Alg. 6)
@@ -1296,8 +1363,11 @@ void Solver::leftmost(int nev, double tol, double* evals, double* evecs) {
     eps_op[k] = k == 0 ? tol : 0.1 * h_.eps[k];
     mu_re[k] = k + 1 <= K ? alpha * h_.eps[k + 1] : 0.0;
     mu_ex[k] = beta * h_.eps[k];
-    dd[k] = std::max(1, std::min(nlev(k) / 10, nev / 10));
+    dd[k] = o_.d > 0 ? std::min(o_.d, nlev(k)) : std::max(1, std::min(nlev(k) / 10, nev / 10));
   }
+  const int stop = o_.stop_level;
+  MMD_REQUIRE(stop >= 0 && stop <= K, MMD_EINVAL,
+              "stop_level must lie between 0 and the number of coarse levels");
   if (st_) {
     std::memset(st_, 0, sizeof(eig_stats));
     st_->K = K;
@@ -1322,6 +1392,9 @@ void Solver::leftmost(int nev, double tol, double* evals, double* evecs) {
     int keep = 0;
     for (int i = 0; i < nk; ++i)
       if (1.0 / lam[i] >= mu_ex[K]) ++keep;
+    // the coarse-level approximation on the coarsest level itself returns the
+    // nev leading pairs of the dense problem (Section 7.3), no threshold
+    if (stop == K) keep = nk;
     keep = std::min(keep, nev);
     std::vector<double> Zk((size_t)nk * std::max(keep, 1));
     for (int i = 0; i < nk; ++i)
@@ -1334,9 +1407,13 @@ void Solver::leftmost(int nev, double tol, double* evals, double* evecs) {
     sync();
     if (st_) st_->ext_out[K] = keep;
   }
-  for (int k = K - 1; k >= 0; --k) {
+  for (int k = K - 1; k >= stop; --k) {
     const auto tl = std::chrono::steady_clock::now();
     cur_level_ = k;
+    // the level returned by the coarse-level approximation: OP accurate to
+    // eps^(k) in mu units, i.e. relative eps^(k) / mu_1 (mu_1 = 1 under the
+    // paper's scaling, where the two readings coincide)
+    if (k == stop && k > 0 && m > 0) tpcg_[k] = std::min(0.1, eps_op[k] / D[0]);
     // reform V <- Psi^(k+1) V
     const int nk = nlev(k);
     double* Vn = pool_.d(V == pool_.d("VA", 0) ? "VB" : "VA", (size_t)nk * std::max(m, 1));
@@ -1346,10 +1423,24 @@ void Solver::leftmost(int nev, double tol, double* evals, double* evecs) {
     extend(k, V, D, m, nev, eps_op[k], mu_ex[k], dd[k], k == 0);
     if (st_) st_->seconds_level[k] = std::chrono::duration<double>(std::chrono::steady_clock::now() - tl).count();
   }
+  if (stop > 0) {
+    // coarse-level approximation: the level-stop pairs (with missed copies
+    // of repeated eigenvalues swapped in), lifted to level 0
+    if (stop < K) {
+      PhaseTimer pt(st_, 7, s_);
+      multiplicity_check(stop, V, D, m, eps_op[stop], dd[stop]);
+    }
+    coarse_output(V, D, m, stop, nev, evals, evecs);
+    if (st_) {
+      st_->nconv = nev;
+      st_->seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return;
+  }
   if (K == 0) extend(0, V, D, m, nev, tol, 0.0, dd[0], true);
   {
     PhaseTimer pt(st_, 7, s_);
-    multiplicity_check(V, D, m, tol, dd[0]);
+    multiplicity_check(0, V, D, m, tol, dd[0]);
     final_pairs(V, D, m, nev, tol, evals, evecs);
   }
   if (st_) {
@@ -1362,12 +1453,13 @@ void Solver::leftmost(int nev, double tol, double* evals, double* evecs) {
 void Solver::apply_op(int level, int op, const double* Xu, double* Yu, int b) {
   MMD_REQUIRE(level >= 0 && level <= h_.K, MMD_EINVAL, "level out of range");
   MMD_REQUIRE(b > 0, MMD_EINVAL, "b must be positive");
-  MMD_REQUIRE(op >= 0 && op <= 5, MMD_EINVAL, "unknown operator");
+  MMD_REQUIRE(op >= 0 && op <= 6, MMD_EINVAL, "unknown operator");
+  MMD_REQUIRE(op != 6 || level == 0, MMD_EINVAL, "the FP32 operator exists on level 0 only");
   // level-0 vectors are in the caller's numbering at the boundary
   const bool perm = level == 0 && !h_.perm.empty();
   const int n0 = nlev(0);
-  const bool in0 = perm && (op == 0 || op == 1 || op == 4);
-  const bool out0 = perm && (op == 0 || op == 1 || op == 3 || op == 5);
+  const bool in0 = perm && (op == 0 || op == 1 || op == 4 || op == 6);
+  const bool out0 = perm && (op == 0 || op == 1 || op == 3 || op == 5 || op == 6);
   const double* X = Xu;
   double* Y = Yu;
   if (in0) {
@@ -1395,6 +1487,27 @@ void Solver::apply_op(int level, int op, const double* Xu, double* Yu, int b) {
       MMD_REQUIRE(level < h_.K, MMD_EINVAL, "Psi needs a coarser level");
       spmm(h_.dev[level + 1].Psi, X, b, Y, b, b, s_);
       break;
+    case 6: {
+      // the FP32 kernel of the mixed-precision solves: X rounded to FP32, the
+      // first (beta-free) fused CG step Y = A32 X32, Y widened to FP64
+      ensure32();
+      const int ld32 = even_ld(b);
+      float* X32 = pool_.f("ap:x32", (size_t)n0 * ld32);
+      float* Y32 = pool_.f("ap:y32", (size_t)n0 * ld32);
+      float* P32 = pool_.f("ap:p32", (size_t)n0 * ld32);
+      double* part = pool_.d("ap:part", (size_t)kRedBlocks * b);
+      double* bet = pool_.d("ap:beta", b);
+      int* ids = pool_.i("ap:ids", b);
+      std::vector<int> id(b);
+      std::iota(id.begin(), id.end(), 0);
+      h2d(ids, id.data(), b);
+      gather_to32(X, b, ids, X32, ld32, n0, b, s_);
+      spmm32_cg(h_.dev[0].A32, X32, ld32, Y32, ld32, b, true, bet, P32, ld32, part, s_);
+      zero_block(Y, b, n0, b, s_);
+      scatter_add64(Y32, ld32, ids, ids, Y, b, n0, b, s_);
+      sync();  // id (host) must outlive its copy
+      break;
+    }
     default: throw Error(MMD_EINVAL, "unknown operator");
   }
   if (out0) permute_rows(Y, b, Yu, b, n0, b, h_.d_perm.p, true, s_);

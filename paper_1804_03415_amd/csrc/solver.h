@@ -109,12 +109,18 @@ class Solver {
   void restart(Lanczos& L, int kkeep, int p);
   void extend(int k, double*& V, std::vector<double>& D, int& m, int m_tar, double eps,
               double mu_ex, int d, bool relative);
-  void multiplicity_check(double*& V, std::vector<double>& D, int m, double eps, int d);
+  void multiplicity_check(int k, double*& V, std::vector<double>& D, int m, double eps, int d);
   void refine(int k, double*& V, std::vector<double>& D, int& m, double eps, double mu_h,
               double lam_max_M, double gamma);
   void mqr(int k, double* F, int n, int b, const std::string& tag);
   void final_pairs(double* V, const std::vector<double>& D, int m, int nev, double tol,
                    double* evals, double* evecs);
+  // returned pairs: row-major level-0 block Vn (n x nev) -> caller's layout
+  void emit_pairs(const double* Vn, const std::vector<double>& lam, int nev, double* evals,
+                  double* evecs);
+  // stop_level > 0: lift the level-k pairs to level 0 and return them
+  void coarse_output(const double* V, const std::vector<double>& D, int m, int k, int nev,
+                     double* evals, double* evecs);
 
   void sync() {
     MMD_HIP(hipStreamSynchronize(s_));

