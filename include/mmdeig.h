@@ -233,6 +233,19 @@ int mmd_solve(mmd_handle* h, int32_t level, int32_t kind, const double* rhs, dou
 int mmdk_spmm(int64_t n_rows, int64_t n_cols, const int64_t* rowptr, const int32_t* colind,
               const double* val, const double* X, double* Y, int32_t b, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as mmdk_spmm, same arguments and layouts, with no hipMalloc, hipFree
+ * or allocating library call.  The int32 copy of the row pointers goes to a
+ * library-owned device array of fixed size (n_rows <= 4194304, 16 MiB held on
+ * every GPU the library runs on until the process ends); larger inputs return
+ * MMD_EINVAL before any device work.  Every call on one GPU shares that array:
+ * calls that overlap on the same GPU race.  The call reads nnz from the
+ * device row pointers and synchronises hip_stream, as mmdk_spmm does. */
+int mmdk_spmm_noalloc(int64_t n_rows, int64_t n_cols, const int64_t* rowptr,
+                      const int32_t* colind, const double* val, const double* X, double* Y,
+                      int32_t b, void* hip_stream);
+
 /* Release a handle and everything it owns (NULL is ignored). */
 void mmd_free(mmd_handle* h);
 

@@ -279,3 +279,15 @@ def spmm(rowptr, col, val, X, n_cols=None, stream=None):
                           _lib._ptr(X), _lib._ptr(Y), b, _lib._stream(stream)))
     return Y
 
+
+def spmm_noalloc(rowptr, col, val, X, Y, n_cols=None, stream=None):
+    """Y = A X through mmdk_spmm_noalloc: the caller provides Y (CUDA float64
+    [n_rows, b]); the library allocates nothing (its row-pointer staging is a
+    fixed device array, at most 4194304 rows).  Returns Y."""
+    n_rows = rowptr.numel() - 1
+    n_cols = X.shape[0] if n_cols is None else n_cols
+    b = X.shape[1]
+    check(lib().mmdk_spmm_noalloc(n_rows, n_cols, _lib._ptr(rowptr), _lib._ptr(col),
+                                  _lib._ptr(val), _lib._ptr(X), _lib._ptr(Y), b,
+                                  _lib._stream(stream)))
+    return Y

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmmdeig.so")
-SOURCES = ["kernels.hip", "pcg_persistent.hip", "mixed.hip", "dense.cpp", "mmd_build.cpp", "solver.cpp", "backward.cpp", "batch.cpp",
+SOURCES = ["kernels.hip", "pcg_persistent.hip", "mixed.hip", "noalloc.hip", "dense.cpp", "mmd_build.cpp", "solver.cpp", "backward.cpp", "batch.cpp",
            "capi.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-fopenmp", "-Wall", "-Wno-unused-result",

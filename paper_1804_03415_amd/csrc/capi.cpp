@@ -5,6 +5,7 @@
 
 #include "batch.h"
 #include "handle.h"
+#include "noalloc.h"
 #include "solver.h"
 
 namespace mmd {
@@ -168,32 +169,60 @@ int mmd_solve(mmd_handle* h, int32_t level, int32_t kind, const double* rhs, dou
   });
 }
 
+namespace {
+// Shared body of mmdk_spmm and mmdk_spmm_noalloc: ptr32 receives the int32
+// copy of the caller's row pointers (n_rows + 1 entries).
+void spmm_caller_csr(int64_t n_rows, int64_t n_cols, const int64_t* rowptr, const int32_t* colind,
+                     const double* val, const double* X, double* Y, int32_t b, hipStream_t s,
+                     int* ptr32) {
+  int64_t nnz = 0;
+  MMD_HIP(hipMemcpyAsync(&nnz, rowptr + n_rows, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MMD_HIP(hipStreamSynchronize(s));
+  MMD_REQUIRE(nnz >= 0 && nnz < (int64_t(1) << 31), MMD_EINVAL, "nnz out of range");
+  mmd::i64_to_i32(rowptr, ptr32, n_rows + 1, s);
+  mmd::CsrView A;
+  A.n_rows = static_cast<int>(n_rows);
+  A.n_cols = static_cast<int>(n_cols);
+  A.nnz = nnz;
+  A.rowptr = ptr32;
+  A.col = colind;
+  A.val = val;
+  A.avg_row = n_rows ? static_cast<double>(nnz) / n_rows : 1.0;
+  mmd::spmm(A, X, b, Y, b, b, s);
+  MMD_HIP(hipStreamSynchronize(s));
+}
+
+void check_spmm_args(int64_t n_rows, int64_t n_cols, int32_t b) {
+  MMD_REQUIRE(n_rows >= 0 && n_rows < (int64_t(1) << 31) && n_cols >= 0 &&
+                  n_cols < (int64_t(1) << 31),
+              MMD_EINVAL, "dimension out of range");
+  MMD_REQUIRE(b > 0, MMD_EINVAL, "b must be positive");
+}
+}  // namespace
+
 int mmdk_spmm(int64_t n_rows, int64_t n_cols, const int64_t* rowptr, const int32_t* colind,
               const double* val, const double* X, double* Y, int32_t b, void* hip_stream) {
   return guarded([&] {
-    MMD_REQUIRE(n_rows >= 0 && n_rows < (int64_t(1) << 31) && n_cols >= 0 &&
-                    n_cols < (int64_t(1) << 31),
-                MMD_EINVAL, "dimension out of range");
-    MMD_REQUIRE(b > 0, MMD_EINVAL, "b must be positive");
+    check_spmm_args(n_rows, n_cols, b);
     if (n_rows == 0) return;
     MMD_REQUIRE(rowptr && X && Y, MMD_EINVAL, "null argument");
-    const auto s = static_cast<hipStream_t>(hip_stream);
-    int64_t nnz = 0;
-    MMD_HIP(hipMemcpyAsync(&nnz, rowptr + n_rows, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    MMD_HIP(hipStreamSynchronize(s));
-    MMD_REQUIRE(nnz >= 0 && nnz < (int64_t(1) << 31), MMD_EINVAL, "nnz out of range");
     mmd::DBuf<int> ptr32(n_rows + 1);
-    mmd::i64_to_i32(rowptr, ptr32.p, n_rows + 1, s);
-    mmd::CsrView A;
-    A.n_rows = static_cast<int>(n_rows);
-    A.n_cols = static_cast<int>(n_cols);
-    A.nnz = nnz;
-    A.rowptr = ptr32.p;
-    A.col = colind;
-    A.val = val;
-    A.avg_row = n_rows ? static_cast<double>(nnz) / n_rows : 1.0;
-    mmd::spmm(A, X, b, Y, b, b, s);
-    MMD_HIP(hipStreamSynchronize(s));
+    spmm_caller_csr(n_rows, n_cols, rowptr, colind, val, X, Y, b,
+                    static_cast<hipStream_t>(hip_stream), ptr32.p);
+  });
+}
+
+int mmdk_spmm_noalloc(int64_t n_rows, int64_t n_cols, const int64_t* rowptr,
+                      const int32_t* colind, const double* val, const double* X, double* Y,
+                      int32_t b, void* hip_stream) {
+  return guarded([&] {
+    check_spmm_args(n_rows, n_cols, b);
+    MMD_REQUIRE(n_rows <= mmd::kNoAllocMaxRows, MMD_EINVAL,
+                "mmdk_spmm_noalloc: n_rows exceeds the scratch capacity of 4194304 rows");
+    if (n_rows == 0) return;
+    MMD_REQUIRE(rowptr && X && Y, MMD_EINVAL, "null argument");
+    spmm_caller_csr(n_rows, n_cols, rowptr, colind, val, X, Y, b,
+                    static_cast<hipStream_t>(hip_stream), mmd::noalloc_scratch_rowptr32());
   });
 }
 
