@@ -233,6 +233,21 @@ int mmd_solve(mmd_handle* h, int32_t level, int32_t kind, const double* rhs, dou
 int mmdk_spmm(int64_t n_rows, int64_t n_cols, const int64_t* rowptr, const int32_t* colind,
               const double* val, const double* X, double* Y, int32_t b, void* hip_stream);
 
+/* The dense tall-skinny products of the Rayleigh-Ritz and restart steps on
+ * the FP64 matrix cores: C = X^T Y (the M-inner-product Gram matrices of the
+ * M-orthogonal QR and S = W^T F of Alg. 5) and Z = alpha X C + beta Z (the
+ * rotations V Q of Alg. 2 and Q P, F P of Alg. 5).  Device row-major
+ * operands: X [n x m] (ld ldx >= m), Y [n x p] (ldy >= p), C [m x p]
+ * (ldc >= p), Z [n x p] (ldz >= p).  mmdk_gram splits the n rows into chunks
+ * whose partial products it sums in a library-allocated workspace.  Both
+ * synchronise hip_stream before returning.  Errors: MMD_EINVAL, MMD_ENOMEM,
+ * MMD_EHIP. */
+int mmdk_gram(int64_t n, int32_t m, int32_t p, const double* X, int32_t ldx, const double* Y,
+              int32_t ldy, double* C, int32_t ldc, void* hip_stream);
+int mmdk_gemm(int64_t n, int32_t m, int32_t p, double alpha, const double* X, int32_t ldx,
+              const double* C, int32_t ldc, double beta, double* Z, int32_t ldz,
+              void* hip_stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * product as mmdk_spmm, same arguments and layouts, with no hipMalloc, hipFree

@@ -106,6 +106,8 @@ def lib():
     L.mmd_solve.argtypes = [vp, i32, i32, vp, vp, i32, i32, dbl, vp, vp]
     L.mmdk_spmm.argtypes = [i64, i64, vp, vp, vp, vp, vp, i32, vp]
     L.mmdk_spmm_noalloc.argtypes = [i64, i64, vp, vp, vp, vp, vp, i32, vp]
+    L.mmdk_gram.argtypes = [i64, i32, i32, vp, i32, vp, i32, vp, i32, vp]
+    L.mmdk_gemm.argtypes = [i64, i32, i32, dbl, vp, i32, vp, i32, dbl, vp, i32, vp]
     L.eig_backward.argtypes = [vp, i32, vp, vp, vp, vp, dbl, vp, vp]
     L.eig_leftmost_batched.argtypes = [i32, vp, vp, dbl, ctypes.POINTER(eig_opts), vp, vp, vp,
                                        vp]
@@ -113,7 +115,7 @@ def lib():
     L.mmd_free.restype = None
     L.mmd_last_error.restype = ctypes.c_char_p
     for f in ("mmd_build", "mmd_info", "mmd_export", "eig_leftmost", "mmd_apply", "mmd_solve",
-              "mmdk_spmm", "mmdk_spmm_noalloc", "eig_backward", "eig_leftmost_batched"):
+              "mmdk_spmm", "mmdk_spmm_noalloc", "mmdk_gram", "mmdk_gemm", "eig_backward", "eig_leftmost_batched"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L

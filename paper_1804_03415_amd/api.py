@@ -291,3 +291,29 @@ def spmm_noalloc(rowptr, col, val, X, Y, n_cols=None, stream=None):
                                   _lib._ptr(val), _lib._ptr(X), _lib._ptr(Y), b,
                                   _lib._stream(stream)))
     return Y
+
+
+def gram(X, Y, stream=None):
+    """C = X^T Y for row-major CUDA float64 X [n, m] and Y [n, p] (FP64 MFMA)."""
+    import torch
+    X, Y = X.contiguous(), Y.contiguous()
+    n, m = X.shape
+    p = Y.shape[1]
+    C = torch.empty((m, p), dtype=torch.float64, device=X.device)
+    check(lib().mmdk_gram(n, m, p, _lib._ptr(X), m, _lib._ptr(Y), p, _lib._ptr(C), p,
+                          _lib._stream(stream)))
+    return C
+
+
+def gemm(X, C, Z=None, alpha=1.0, beta=0.0, stream=None):
+    """Z = alpha X C + beta Z for row-major CUDA float64 X [n, m], C [m, p]
+    (FP64 MFMA); Z is created when not given (then beta must be 0)."""
+    import torch
+    X, C = X.contiguous(), C.contiguous()
+    n, m = X.shape
+    p = C.shape[1]
+    if Z is None:
+        Z = torch.empty((n, p), dtype=torch.float64, device=X.device)
+    check(lib().mmdk_gemm(n, m, p, alpha, _lib._ptr(X), m, _lib._ptr(C), p, beta, _lib._ptr(Z),
+                          p, _lib._stream(stream)))
+    return Z

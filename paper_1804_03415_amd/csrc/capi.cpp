@@ -1,5 +1,6 @@
 // C-ABI entry points (declared in include/mmdeig.h).  Each call converts
 // exceptions into a status code and a thread-local message.
+#include <algorithm>
 #include <cstring>
 #include <string>
 
@@ -223,6 +224,36 @@ int mmdk_spmm_noalloc(int64_t n_rows, int64_t n_cols, const int64_t* rowptr,
     MMD_REQUIRE(rowptr && X && Y, MMD_EINVAL, "null argument");
     spmm_caller_csr(n_rows, n_cols, rowptr, colind, val, X, Y, b,
                     static_cast<hipStream_t>(hip_stream), mmd::noalloc_scratch_rowptr32());
+  });
+}
+
+int mmdk_gram(int64_t n, int32_t m, int32_t p, const double* X, int32_t ldx, const double* Y,
+              int32_t ldy, double* C, int32_t ldc, void* hip_stream) {
+  return guarded([&] {
+    MMD_REQUIRE(n >= 0 && n < (int64_t(1) << 31) && m >= 0 && p >= 0, MMD_EINVAL,
+                "dimension out of range");
+    MMD_REQUIRE(ldx >= m && ldy >= p && ldc >= p, MMD_EINVAL, "leading dimension too small");
+    if (m == 0 || p == 0) return;
+    MMD_REQUIRE(C && (n == 0 || (X && Y)), MMD_EINVAL, "null argument");
+    const auto s = static_cast<hipStream_t>(hip_stream);
+    mmd::DBuf<double> work(std::max<size_t>(1, mmd::gram_work_size(static_cast<int>(n), m, p)));
+    mmd::gram(X, ldx, Y, ldy, static_cast<int>(n), m, p, C, ldc, work.p, s);
+    MMD_HIP(hipStreamSynchronize(s));
+  });
+}
+
+int mmdk_gemm(int64_t n, int32_t m, int32_t p, double alpha, const double* X, int32_t ldx,
+              const double* Cm, int32_t ldc, double beta, double* Z, int32_t ldz,
+              void* hip_stream) {
+  return guarded([&] {
+    MMD_REQUIRE(n >= 0 && n < (int64_t(1) << 31) && m >= 0 && p >= 0, MMD_EINVAL,
+                "dimension out of range");
+    MMD_REQUIRE(ldx >= m && ldc >= p && ldz >= p, MMD_EINVAL, "leading dimension too small");
+    if (n == 0 || p == 0) return;
+    MMD_REQUIRE(Z && (m == 0 || (X && Cm)), MMD_EINVAL, "null argument");
+    const auto s = static_cast<hipStream_t>(hip_stream);
+    mmd::gemm_nn(X, ldx, Cm, ldc, Z, ldz, static_cast<int>(n), m, p, alpha, beta, s);
+    MMD_HIP(hipStreamSynchronize(s));
   });
 }
 

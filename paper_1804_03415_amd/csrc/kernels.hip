@@ -997,9 +997,36 @@ __global__ void k_i64_to_i32(const int64_t* __restrict__ src, int* __restrict__ 
 }
 
 // ------------------------------------------------------------------ FP64 GEMMs
-// 64 x 64 output tile, 256 threads in a 16 x 16 grid, 4 x 4 outputs per thread
-// at stride 16 (conflict-free LDS reads), K staged 16 at a time through LDS.
+// Both tall-skinny products run on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64, D[16x16] += A[16x4] B[4x16]).  A workgroup of four
+// wavefronts owns a 64 x 64 output tile; the two operand tiles are staged
+// through LDS 16 deep along the contracted index, and each wavefront
+// accumulates one 32 x 32 quadrant as 2 x 2 MFMA tiles, 4 MFMA steps per stage.
+// Lane layout of the instruction (lane l = 0..63): A[l % 16][l / 16],
+// B[l / 16][l % 16], D[l / 16 + 4 r][l % 16] in accumulator element r
+// (measured on gfx950).
 constexpr int TM = 64, TK = 16;
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// acc[ti][tj] += sum_k as[k][row0 + 16 ti + i] * bs[k][col0 + 16 tj + j] over the
+// TK staged values of k (as, bs: [TK][ld] in LDS)
+template <int LDA, int LDB>
+__device__ inline void mfma_quadrant(const double (*as)[LDA], const double (*bs)[LDB], int row0,
+                                     int col0, v4d acc[2][2]) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int i = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int k0 = 0; k0 < TK; k0 += 4) {
+    const double a0 = as[k0 + kq][row0 + i];
+    const double a1 = as[k0 + kq][row0 + 16 + i];
+    const double b0 = bs[k0 + kq][col0 + i];
+    const double b1 = bs[k0 + kq][col0 + 16 + i];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+  }
+}
 
 __global__ __launch_bounds__(kBlock) void k_gram(const double* __restrict__ X, int ldx,
                                                  const double* __restrict__ Y, int ldy, int n,
@@ -1007,11 +1034,16 @@ __global__ __launch_bounds__(kBlock) void k_gram(const double* __restrict__ X, i
                                                  double* __restrict__ work) {
   __shared__ double xs[TK][TM];
   __shared__ double ys[TK][TM];
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   const int i0 = blockIdx.x * TM, j0 = blockIdx.y * TM;
   const int r0 = blockIdx.z * chunk;
   const int r1 = min(n, r0 + chunk);
-  double acc[4][4] = {};
+  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int qi = 32 * (w >> 1), qj = 32 * (w & 1);  // this wavefront's quadrant
+  v4d acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
   for (int k0 = r0; k0 < r1; k0 += TK) {
     for (int q = threadIdx.x; q < TK * TM; q += kBlock) {
       const int kk = q / TM, cc = q % TM;
@@ -1020,29 +1052,20 @@ __global__ __launch_bounds__(kBlock) void k_gram(const double* __restrict__ X, i
       ys[kk][cc] = (row < r1 && j0 + cc < p) ? Y[(size_t)row * ldy + j0 + cc] : 0.0;
     }
     __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < TK; ++kk) {
-      double a[4], bb[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        a[u] = xs[kk][ty + 16 * u];
-        bb[u] = ys[kk][tx + 16 * u];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * bb[v];
-    }
+    mfma_quadrant<TM, TM>(xs, ys, qi, qj, acc);
     __syncthreads();
   }
-  double* w = work + (size_t)blockIdx.z * m * p;
+  double* wk = work + (size_t)blockIdx.z * m * p;
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = i0 + ty + 16 * u, j = j0 + tx + 16 * v;
-      if (i < m && j < p) w[(size_t)i * p + j] = acc[u][v];
-    }
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + qi + 16 * a + (lane >> 4) + 4 * r;
+        const int j = j0 + qj + 16 * b + (lane & 15);
+        if (i < m && j < p) wk[(size_t)i * p + j] = acc[a][b][r];
+      }
 }
 
 __global__ void k_gram_reduce(const double* __restrict__ work, int splits, int m, int p,
@@ -1060,9 +1083,14 @@ __global__ __launch_bounds__(kBlock) void k_gemm_nn(const double* __restrict__ X
                                                     int m, int p, double alpha, double beta) {
   __shared__ double xs[TK][TM + 1];
   __shared__ double cs[TK][TM];
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   const int i0 = blockIdx.x * TM, j0 = blockIdx.y * TM;
-  double acc[4][4] = {};
+  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int qi = 32 * (w >> 1), qj = 32 * (w & 1);
+  v4d acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < m; k0 += TK) {
     for (int q = threadIdx.x; q < TK * TM; q += kBlock) {
       const int rr = q / TK, kk = q % TK;  // X tile: 64 rows x 16 k, k fastest
@@ -1073,32 +1101,23 @@ __global__ __launch_bounds__(kBlock) void k_gemm_nn(const double* __restrict__ X
       cs[kc][cc] = (k2 < m && j < p) ? C[(size_t)k2 * ldc + j] : 0.0;
     }
     __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < TK; ++kk) {
-      double a[4], bb[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        a[u] = xs[kk][ty + 16 * u];
-        bb[u] = cs[kk][tx + 16 * u];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * bb[v];
-    }
+    mfma_quadrant<TM + 1, TM>(xs, cs, qi, qj, acc);
     __syncthreads();
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = i0 + ty + 16 * u, j = j0 + tx + 16 * v;
-      if (i < n && j < p) {
-        const size_t iz = (size_t)i * ldz + j;
-        const double old = beta == 0.0 ? 0.0 : beta * Z[iz];
-        Z[iz] = alpha * acc[u][v] + old;
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + qi + 16 * a + (lane >> 4) + 4 * r;
+        const int j = j0 + qj + 16 * b + (lane & 15);
+        if (i < n && j < p) {
+          const size_t iz = (size_t)i * ldz + j;
+          const double old = beta == 0.0 ? 0.0 : beta * Z[iz];
+          Z[iz] = alpha * acc[a][b][r] + old;
+        }
       }
-    }
 }
 
 // thread c of a block sums its column over one chunk of rows, four rows per

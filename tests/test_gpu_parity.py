@@ -541,3 +541,30 @@ def test_coarse_level_approximation(torch_cuda, case):
             assert np.max(np.abs(mu - 1.0 / w[:nev])) <= 1.1 * eps_k
             R = Ainv @ Vh - Vh / w[None, :nev]
             assert np.max(np.linalg.norm(R, axis=0)) <= 2.2 * eps_k
+
+
+# ------------------------------------------------------------------- FP64 MFMA products (a8)
+@pytest.mark.parametrize("n,m,p", [(1, 1, 1), (5, 7, 3), (1000, 16, 16), (4099, 65, 33),
+                                   (100003, 300, 300), (20000, 301, 17)])
+def test_mfma_gram_and_gemm(torch_cuda, n, m, p):
+    """C = X^T Y and Z = alpha X C + beta Z on the FP64 matrix cores, entry by
+    entry against numpy FP64, within the worst-case rounding of a length-k
+    FP64 dot product, (k + 16) u (|X|^T |Y|) (k = n or m): a wrong lane layout
+    or tile index gives O(1) errors.  Shapes cover single elements, partial
+    16 x 16 MFMA tiles, partial 64 x 64 workgroup tiles and the refinement's
+    300-column blocks over 1e5 rows."""
+    torch = torch_cuda
+    from paper_1804_03415_amd import gemm, gram
+    u = 2.0 ** -52
+    X = wl.random_block(n, m, seed=n + m)
+    Y = wl.random_block(n, p, seed=n + p + 1)
+    C = gram(_t(torch, X), _t(torch, Y)).cpu().numpy()
+    ref = X.T @ Y
+    bound = (n + 16) * u * (np.abs(X).T @ np.abs(Y))
+    assert np.all(np.abs(C - ref) <= bound)
+    Cm = wl.random_block(m, p, seed=m * p)
+    Z0 = wl.random_block(n, p, seed=7)
+    Z = gemm(_t(torch, X), _t(torch, Cm), _t(torch, Z0), alpha=-0.5, beta=2.0).cpu().numpy()
+    ref = -0.5 * (X @ Cm) + 2.0 * Z0
+    bound = (m + 16) * u * (0.5 * np.abs(X) @ np.abs(Cm) + 2.0 * np.abs(Z0))
+    assert np.all(np.abs(Z - ref) <= bound)
