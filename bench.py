@@ -53,11 +53,14 @@ def parse():
     ap.add_argument("--traffic-bytes", type=float, default=None,
                     help="HBM bytes per launch of the dominant kernel from rocprofv3 counters")
     ap.add_argument("--verbose", type=int, default=0)
-    ap.add_argument("--workload", default="rgg", choices=["rgg", "knn-backward", "rgg-batch"],
+    ap.add_argument("--workload", default="rgg",
+                    choices=["rgg", "knn-backward", "rgg-batch", "gram"],
                     help="rgg: the leftmost-300 eigensolve of the n = 1e5 RGG (default); "
                          "knn-backward: forward (20 pairs) and eigen-backward of the "
                          "n = 2e5 kNN-GMM graph; rgg-batch: 100 pairs of each of a batch "
-                         "of RGGs with sizes uniform in [5000, 50000]")
+                         "of RGGs with sizes uniform in [5000, 50000]; gram: the FP64 MFMA "
+                         "Gram X^T Y and projection X C products at the 64^3 diffusion "
+                         "refinement shape (n = 262144, 500 columns)")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--streams", type=int, default=8)
     ap.add_argument("--batch-sequential", type=int, default=1,
@@ -263,6 +266,47 @@ def rgg_batch(a):
     print(json.dumps(res), flush=True)
 
 
+def gram_products(a):
+    """TFLOP/s of the FP64 MFMA tall-skinny products (mmdk_gram, mmdk_gemm) at
+    the refinement block shape of the 500-pair 64^3 diffusion solve, against
+    the 78.6 TFLOP/s FP64 matrix peak, timed with HIP events on the stream
+    the library launches on (torch's current stream)."""
+    import torch
+    from paper_1804_03415_amd import gemm, gram
+    n, m = 262144, 500
+    g = torch.Generator(device="cuda").manual_seed(0)
+    X = torch.rand((n, m), dtype=torch.float64, device="cuda", generator=g) - 0.5
+    Y = torch.rand((n, m), dtype=torch.float64, device="cuda", generator=g) - 0.5
+    Cm = torch.rand((m, m), dtype=torch.float64, device="cuda", generator=g) - 0.5
+    Z = torch.empty((n, m), dtype=torch.float64, device="cuda")
+    out = {}
+    for name, fn in (("gram X^T Y", lambda: gram(X, Y)), ("gemm X C", lambda: gemm(X, Cm, Z))):
+        for _ in range(a.warmup + 1):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(a.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / a.steps
+        tf = 2.0 * n * m * m / (ms * 1e-3) / 1e12
+        out[name] = {"ms": round(ms, 3), "tflops": round(tf, 2), "frac": round(tf / 78.6, 4)}
+        print("%s: %.3f ms, %.2f TFLOP/s" % (name, ms, tf), file=sys.stderr, flush=True)
+    ref = (X.T @ Y)
+    err = float((gram(X, Y) - ref).abs().max() / ref.abs().max())
+    res = {"metric": "FP64 MFMA tall-skinny products (n=262144, 500 columns)",
+           "value": out["gram X^T Y"]["tflops"], "unit": "TFLOP/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": out["gram X^T Y"]["ms"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic", "config": {"workload": "gram_n262144_m500", "n": n, "m": m},
+           "roofline": {"bound": "mfma", "achieved": out["gram X^T Y"]["tflops"], "peak": 78.6,
+                        "unit": "TFLOP/s", "frac": out["gram X^T Y"]["frac"], "traffic": None},
+           "products": out, "max_rel_diff_vs_torch_matmul": err}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -287,6 +331,8 @@ def main():
         return knn_backward(a)
     if a.workload == "rgg-batch":
         return rgg_batch(a)
+    if a.workload == "gram":
+        return gram_products(a)
     p = workloads.rgg(a.n, 0)
     t = time.perf_counter()
     dec = Decomposition.from_problem(p, levels=a.levels, targets=(4, 8))

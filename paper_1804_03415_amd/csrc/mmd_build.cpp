@@ -595,6 +595,40 @@ std::vector<int> patch_rcm(const HostCSR& A, const Patches& P) {
   return order;
 }
 
+// Strip order of the patches of a 2-D point set: patch centroids in
+// vertical strips about two patch diameters wide, bottom to top and top to
+// bottom in alternate strips.  Every neighbour of a row then lies within about
+// one and a half strip lengths of it in the order, a band that stays in one
+// XCD's L2 while the XCD sweeps its contiguous range of rows.
+std::vector<int> patch_strips(const std::vector<double>& xy, const Patches& P) {
+  const int m = static_cast<int>(P.size());
+  std::vector<double> cx(m), cy(m);
+  double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+  for (int j = 0; j < m; ++j) {
+    double a = 0.0, b = 0.0;
+    for (int v : P[j]) {
+      a += xy[2 * (size_t)v];
+      b += xy[2 * (size_t)v + 1];
+    }
+    cx[j] = a / P[j].size();
+    cy[j] = b / P[j].size();
+    x0 = std::min(x0, cx[j]);
+    x1 = std::max(x1, cx[j]);
+    y0 = std::min(y0, cy[j]);
+    y1 = std::max(y1, cy[j]);
+  }
+  const double area = std::max((x1 - x0) * (y1 - y0), 1e-300);
+  const double w = 2.0 * std::sqrt(area / std::max(m, 1));
+  std::vector<int> strip(m), order(m);
+  for (int j = 0; j < m; ++j) strip[j] = static_cast<int>((cx[j] - x0) / w);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (strip[a] != strip[b]) return strip[a] < strip[b];
+    return (strip[a] & 1) ? cy[a] > cy[b] : cy[a] < cy[b];
+  });
+  return order;
+}
+
 void renumber_level0(mmd_handle& h, Patches& P) {
   LevelHost& L0 = h.host[0];
   const int n = L0.n;
@@ -605,7 +639,11 @@ void renumber_level0(mmd_handle& h, Patches& P) {
   // the tiles of the block SpMM gather few distinct rows; without coordinates
   // reverse Cuthill-McKee keeps neighbouring patches close
   std::vector<int> order;
-  if (!L0.coords.empty()) {
+  const char* env = std::getenv("MMDEIG_L0_ORDER");
+  const std::string mode = env ? env : "";
+  if (!L0.coords.empty() && L0.cdim == 2 && mode == "strip") {
+    order = patch_strips(L0.coords, P);
+  } else if (!L0.coords.empty() && mode != "rcm") {
     order.resize(P.size());
     std::iota(order.begin(), order.end(), 0);
   } else {
