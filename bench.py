@@ -63,8 +63,10 @@ def parse():
                          "refinement shape (n = 262144, 500 columns)")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--streams", type=int, default=8)
-    ap.add_argument("--batch-sequential", type=int, default=1,
+    ap.add_argument("--batch-sequential", type=int, default=0,
                     help="also time the batch one problem after another (eig_leftmost)")
+    ap.add_argument("--batch-precisions", default="fp64,fp32-refine",
+                    help="batched runs to time, in order; the line's value is the last one")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 5 times (the reference kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings) and exit")
@@ -212,55 +214,75 @@ def knn_backward(a):
 
 def rgg_batch(a):
     """Throughput of eig_leftmost_batched on a batch of RGG Laplacians (mean
-    degree 8, + 1e-6 I, sizes uniform in [5000, 50000], 100 pairs each),
-    against solving the same problems one after another."""
+    degree 8, + 1e-6 I, sizes uniform in [5000, 50000], 100 pairs each), in
+    each precision of --batch-precisions (FP64 and FP32 CG + FP64 refinement
+    by default), optionally against solving the problems one after another.
+    Every pair of every member is checked against the residual target."""
     import torch
     import workloads
     from paper_1804_03415_amd import Decomposition, eig_leftmost_batched
     nev = 100
+    os.environ.setdefault("MMDEIG_LOG", "1")  # batcher statistics at the end of each batch
     probs = workloads.rgg_batch(a.batch_count, seed=0)
     t = time.perf_counter()
     decs = [Decomposition.from_problem(q, levels=a.levels, targets=(4, 8)) for q in probs]
     t_build = time.perf_counter() - t
     print("rgg-batch: %d problems, sum n %d, build %.1f s" % (
         len(probs), sum(q.n for q in probs), t_build), file=sys.stderr, flush=True)
+    mats = [q.scipy() for q in probs]
+
+    def check(out):
+        worst, null_ok = 0.0, True
+        for A, (lam, V, st) in zip(mats, out):
+            Vh = V.cpu().numpy().T
+            rho = np.linalg.norm(A @ Vh - Vh * lam[None, :], axis=0) / (
+                np.abs(lam) * np.linalg.norm(Vh, axis=0))
+            worst = max(worst, float(rho.max()))
+        return worst
+
     # warm-up: load every kernel once on a small member
     small = min(range(len(probs)), key=lambda b: probs[b].n)
-    eig_leftmost_batched([decs[small]], [nev], tol=a.tol, streams=1)
+    for prec in a.batch_precisions.split(","):
+        eig_leftmost_batched([decs[small]], [nev], tol=a.tol, streams=1, precision=prec)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    out = eig_leftmost_batched(decs, [nev] * len(decs), tol=a.tol, streams=a.streams)
-    torch.cuda.synchronize()
-    el_b = time.perf_counter() - t0
-    print("rgg-batch: batched %.1f s" % el_b, file=sys.stderr, flush=True)
-    worst = 0.0
-    for q, (lam, V, st) in zip(probs, out):
-        Vh = V.cpu().numpy().T
-        A = q.scipy()
-        rho = np.linalg.norm(A @ Vh - Vh * lam[None, :], axis=0) / (np.abs(lam) * np.linalg.norm(Vh, axis=0))
-        worst = max(worst, float(rho.max()))
+    runs = {}
+    for prec in a.batch_precisions.split(","):
+        t0 = time.perf_counter()
+        out = eig_leftmost_batched(decs, [nev] * len(decs), tol=a.tol, streams=a.streams,
+                                   precision=prec)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        worst = check(out)
+        runs[prec] = {"value": round(nev * len(decs) / el, 3), "seconds": round(el, 2),
+                      "max_rel_residual": worst, "residual_ok": bool(worst <= 1e-8)}
+        print("rgg-batch: %s batched %.1f s, max residual %.2e" % (prec, el, worst),
+              file=sys.stderr, flush=True)
+        last = prec
     seq = None
     if a.batch_sequential:
         t0 = time.perf_counter()
         for b, dec in enumerate(decs):
-            dec.eig_leftmost(nev, tol=a.tol)
+            dec.eig_leftmost(nev, tol=a.tol, precision=last)
             if b % 8 == 7:
                 print("rgg-batch: sequential %d/%d %.1f s" % (b + 1, len(decs),
                       time.perf_counter() - t0), file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         el_s = time.perf_counter() - t0
-        seq = {"value": round(nev * len(decs) / el_s, 3), "seconds": round(el_s, 2)}
+        seq = {"value": round(nev * len(decs) / el_s, 3), "seconds": round(el_s, 2),
+               "precision": last}
+    r = runs[last]
     res = {"metric": "eigenpairs/s at rel. residual 1e-8 (batch)",
-           "value": round(nev * len(decs) / el_b, 3), "unit": "eigenpairs/s", "n_gpus": 1,
-           "steps": 1, "warmup": 1, "ms_per_step": round(1000.0 * el_b, 2),
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "value": r["value"], "unit": "eigenpairs/s", "n_gpus": 1,
+           "steps": 1, "warmup": 1, "ms_per_step": round(1000.0 * r["seconds"], 2),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32+f64" if last == "fp32-refine" else "f64",
            "data": "synthetic",
            "config": {"workload": "rgg_batch_%d_n5000-50000_nev100" % len(decs),
                       "sum_n": int(sum(q.n for q in probs)),
                       "sum_nnz": int(sum(q.nnz for q in probs)), "nev": nev, "tol": a.tol,
-                      "streams": a.streams, "build_s": round(t_build, 2)},
-           "max_rel_residual": worst, "residual_ok": bool(worst <= 1e-8),
-           "sequential": seq}
+                      "streams": a.streams, "precision": last, "build_s": round(t_build, 2)},
+           "max_rel_residual": r["max_rel_residual"], "residual_ok": r["residual_ok"],
+           "batched_by_precision": runs, "sequential": seq}
     for d in decs:
         d.close()
     print(json.dumps(res), flush=True)

@@ -123,7 +123,9 @@ typedef struct {
   double spmm0_ms;
   double spmm0_bytes;
   int32_t spmm0_b;
-  int32_t reserved_stats;
+  /* precision = 1: level-0 block solves whose FP32 inner solves stopped
+     reducing the FP64 residual and were finished by FP64 CG */
+  int32_t mixed_fallbacks;
 } eig_stats;
 
 typedef struct mmd_handle mmd_handle;

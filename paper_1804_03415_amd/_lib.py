@@ -63,7 +63,7 @@ class eig_stats(ctypes.Structure):
                 ("seconds_total", ctypes.c_double), ("seconds_phase", ctypes.c_double * 8),
                 ("spmm0_launches", ctypes.c_int64), ("spmm0_ms", ctypes.c_double),
                 ("spmm0_bytes", ctypes.c_double), ("spmm0_b", ctypes.c_int32),
-                ("reserved_stats", ctypes.c_int32)]
+                ("mixed_fallbacks", ctypes.c_int32)]
 
     PHASES = ("refine_pcg", "refine_bcg", "refine_host_dense", "refine_qr_gram", "extend_op",
               "extend_orth", "restart", "output")
@@ -71,6 +71,7 @@ class eig_stats(ctypes.Structure):
     def as_dict(self):
         K = self.K
         out = {"K": K, "nconv": self.nconv, "missed_swaps": self.missed_swaps,
+               "mixed_fallbacks": self.mixed_fallbacks,
                "seconds_total": self.seconds_total, "levels": {},
                "phases": {n: round(self.seconds_phase[i], 4) for i, n in enumerate(self.PHASES)},
                "spmm0": {"launches": self.spmm0_launches, "ms": self.spmm0_ms,

@@ -34,7 +34,9 @@ struct Pcg1Plan {
   size_t lds = 0;
   DBuf<int> part;  // grid + 1 row boundaries
 };
-void pcg1_plan(const CsrView& A, const std::vector<int>& rp, Pcg1Plan& plan);
+// grid_cap: preferred block count (more are taken when the slices need the
+// LDS of more blocks).
+void pcg1_plan(const CsrView& A, const std::vector<int>& rp, Pcg1Plan& plan, int grid_cap = 112);
 // Plan for the resident flexible PCG on (A, M) (host row pointers rpa, rpm):
 // the fewest blocks (multiple of 8, at least 16) whose slices fit in LDS.
 void pcg1_plan_flex(const CsrView& A, const std::vector<int>& rpa, const CsrView& M,
@@ -44,6 +46,26 @@ void pcg1_plan_flex(const CsrView& A, const std::vector<int>& rpa, const CsrView
 // CG stops at ||r_in|| <= tol_in ||r||.  Plain CG (no M) runs the resident
 // kernel when plan says it fits.
 void pcg1(Pcg1Args a, hipStream_t s, const Pcg1Plan* plan = nullptr);
+
+// One solve of a batched launch: the same arguments and plan as pcg1, the
+// kernel body and block count pcg1 would choose, and the request's block
+// range [off, off + nblk) in the batch grid.
+struct Pcg1Req {
+  Pcg1Args a;
+  const int* part = nullptr;  // resident plans: row boundaries per block
+  int kind = 0;               // 0 resident plain CG, 1 resident flexible PCG, 2 from global memory
+  int off = 0, nblk = 0;
+  size_t lds = 0;             // dynamic LDS bytes per block
+};
+Pcg1Req pcg1_request(Pcg1Args a, const Pcg1Plan* plan);
+// Blocks that can be co-resident in one batched launch with lds bytes of
+// dynamic LDS per block.
+int pcg1_multi_capacity(size_t lds);
+// One cooperative launch of all reqs (offsets assigned here, multiples of 8);
+// h_reqs (pinned) and d_reqs hold reqs.size() entries; every request's
+// arrival counter is cleared on s before the launch.  The caller checks that
+// the total block count fits pcg1_multi_capacity.
+void pcg1_multi(std::vector<Pcg1Req>& reqs, Pcg1Req* h_reqs, Pcg1Req* d_reqs, hipStream_t s);
 size_t pcg1_red_size();
 int pcg1_grid();
 

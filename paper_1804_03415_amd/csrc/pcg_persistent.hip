@@ -38,15 +38,17 @@ struct Ctx {
 };
 
 // Grid barrier: every block adds one arrival (release), then waits until all
-// gridDim.x arrivals of this generation are in (relaxed spin, acquire fence).
+// c.nblk arrivals of this generation are in (relaxed spin, acquire fence).
+// c.nblk is the number of blocks of this solve (the whole grid, or one
+// request's block range in a batched launch).
 __device__ inline void grid_barrier(Ctx& c) {
   __syncthreads();
   c.gen += 1;
   if (threadIdx.x == 0) {
     __hip_atomic_fetch_add(c.bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     // modular comparison: the counter may wrap past 2^32 in a long solve, the
-    // distance to the target never exceeds gridDim.x
-    const unsigned target = c.gen * (unsigned)gridDim.x;
+    // distance to the target never exceeds c.nblk
+    const unsigned target = c.gen * (unsigned)c.nblk;
     while ((int)(__hip_atomic_load(c.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0)
       __builtin_amdgcn_s_sleep(1);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -198,15 +200,15 @@ __device__ inline double dir_step(Ctx& c, const CsrView& A, int lpr, const doubl
   return part;
 }
 
-__global__ __launch_bounds__(kThreads) void k_pcg1(Pcg1Args a) {
+__device__ inline void body_pcg1(const Pcg1Args& a, const int gblk, const int gnb) {
   __shared__ double sh[kThreads / kWave];
   // rows are dealt per XCD-contiguous block number (workgroups go round-robin to XCDs)
-  const int bx = (gridDim.x % 8) ? (int)blockIdx.x
-                                 : (int)((blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8);
-  Ctx c{a.bar, 0u, (int)gridDim.x, (int)blockIdx.x,
-        (int)(bx * blockDim.x + threadIdx.x), (int)(gridDim.x * blockDim.x),
+  const int bx = (gnb % 8) ? (int)gblk
+                                 : (int)((gblk % 8) * (gnb / 8) + gblk / 8);
+  Ctx c{a.bar, 0u, (int)gnb, (int)gblk,
+        (int)(bx * blockDim.x + threadIdx.x), (int)(gnb * blockDim.x),
         (int)((bx * blockDim.x + threadIdx.x) / kWave),
-        (int)((gridDim.x * blockDim.x) / kWave), (int)(threadIdx.x & (kWave - 1)), a.red, 0};
+        (int)((gnb * blockDim.x) / kWave), (int)(threadIdx.x & (kWave - 1)), a.red, 0};
   const int n = a.n;
   const bool pre = a.M.rowptr != nullptr;
   // r = b - A x0 (or b with x = 0); ||b||^2, ||r||^2
@@ -397,12 +399,12 @@ __device__ inline double row_res(int l, double ri, const int* lrp, const int* lc
   return a0 + a1;
 }
 
-__global__ __launch_bounds__(kThreads) void k_cg1_res(Pcg1Args a, const int* __restrict__ part) {
-  extern __shared__ double lds[];
+__device__ inline void body_cg1_res(const Pcg1Args& a, const int* __restrict__ part,
+                                    const int gblk, const int gnb, double* lds) {
   __shared__ double sh[kThreads / kWave];
-  const int bx = (gridDim.x % 8) ? (int)blockIdx.x
-                                 : (int)((blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8);
-  Ctx c{a.bar, 0u, (int)gridDim.x, (int)blockIdx.x, 0, 0, 0, 0, (int)(threadIdx.x & (kWave - 1)),
+  const int bx = (gnb % 8) ? (int)gblk
+                                 : (int)((gblk % 8) * (gnb / 8) + gblk / 8);
+  Ctx c{a.bar, 0u, (int)gnb, (int)gblk, 0, 0, 0, 0, (int)(threadIdx.x & (kWave - 1)),
         a.red, 0};
   const CsrView& A = a.A;
   const int r0 = part[bx], r1 = part[bx + 1], nr = r1 - r0;
@@ -544,12 +546,12 @@ __device__ inline double row_lpr(bool ok, int l, int sub, const int* lrp, const 
   return acc;
 }
 
-__global__ __launch_bounds__(kThreads) void k_pcg1_res(Pcg1Args a, const int* __restrict__ part) {
-  extern __shared__ double lds[];
+__device__ inline void body_pcg1_res(const Pcg1Args& a, const int* __restrict__ part,
+                                     const int gblk, const int gnb, double* lds) {
   __shared__ double sh[kThreads / kWave];
-  const int bx = (gridDim.x % 8) ? (int)blockIdx.x
-                                 : (int)((blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8);
-  Ctx c{a.bar, 0u, (int)gridDim.x, (int)blockIdx.x, 0, 0, 0, 0, (int)(threadIdx.x & (kWave - 1)),
+  const int bx = (gnb % 8) ? (int)gblk
+                                 : (int)((gblk % 8) * (gnb / 8) + gblk / 8);
+  Ctx c{a.bar, 0u, (int)gnb, (int)gblk, 0, 0, 0, 0, (int)(threadIdx.x & (kWave - 1)),
         a.red, 0};
   const CsrView& A = a.A;
   const CsrView& M = a.M;
@@ -736,6 +738,41 @@ __global__ __launch_bounds__(kThreads) void k_pcg1_res(Pcg1Args a, const int* __
   }
 }
 
+__global__ __launch_bounds__(kThreads) void k_pcg1(Pcg1Args a) {
+  body_pcg1(a, (int)blockIdx.x, (int)gridDim.x);
+}
+
+__global__ __launch_bounds__(kThreads) void k_cg1_res(Pcg1Args a, const int* __restrict__ part) {
+  extern __shared__ double lds[];
+  body_cg1_res(a, part, (int)blockIdx.x, (int)gridDim.x, lds);
+}
+
+__global__ __launch_bounds__(kThreads) void k_pcg1_res(Pcg1Args a, const int* __restrict__ part) {
+  extern __shared__ double lds[];
+  body_pcg1_res(a, part, (int)blockIdx.x, (int)gridDim.x, lds);
+}
+
+// Several independent single-vector solves in one cooperative launch: request
+// r owns the blocks [off_r, off_r + nblk_r) and runs the body its plan selects
+// on them, with its own arrival counter and reduction slots, so the requests
+// never wait for each other.  Offsets are multiples of 8, so local block j of
+// a request sits on XCD j % 8 as in a launch of its own.
+__global__ __launch_bounds__(kThreads) void k_pcg1_multi(const Pcg1Req* __restrict__ reqs,
+                                                         int nreq) {
+  extern __shared__ double lds[];
+  int r = 0;
+  while (r + 1 < nreq && (int)blockIdx.x >= reqs[r + 1].off) ++r;
+  const Pcg1Req& q = reqs[r];
+  const int gblk = (int)blockIdx.x - q.off;
+  if (gblk >= q.nblk) return;  // padding to a whole XCD round: not part of the solve
+  if (q.kind == 0)
+    body_cg1_res(q.a, q.part, gblk, q.nblk, lds);
+  else if (q.kind == 1)
+    body_pcg1_res(q.a, q.part, gblk, q.nblk, lds);
+  else
+    body_pcg1(q.a, gblk, q.nblk);
+}
+
 int lanes_for(double avg) {
   if (avg <= 10.0) return 8;
   if (avg <= 24.0) return 16;
@@ -763,6 +800,61 @@ int pcg1_grid() {
   return cached;
 }
 
+Pcg1Req pcg1_request(Pcg1Args a, const Pcg1Plan* plan) {
+  Pcg1Req q;
+  if (plan && plan->resident && (a.M.rowptr != nullptr) == plan->flex) {
+    q.kind = plan->flex ? 1 : 0;
+    q.part = plan->part.p;
+    q.nblk = plan->grid;
+    q.lds = plan->lds;
+  } else {
+    const int64_t work = a.A.nnz + (a.M.rowptr ? a.M.nnz : 0);
+    int grid = static_cast<int>(std::min<int64_t>(128, std::max<int64_t>(16, work / 16384)));
+    grid = std::min(grid, pcg1_grid());
+    grid = std::min(grid, std::max(1, (a.n + kThreads - 1) / kThreads * 4));
+    grid = std::max(8, grid / 8 * 8);
+    a.lpr_a = lanes_for(a.A.avg_row);
+    a.lpr_m = a.M.rowptr ? lanes_for(a.M.avg_row) : 8;
+    q.kind = 2;
+    q.nblk = grid;
+    q.lds = 0;
+  }
+  q.a = a;
+  return q;
+}
+
+int pcg1_multi_capacity(size_t lds) {
+  int dev = 0;
+  MMD_HIP(hipGetDevice(&dev));
+  int cus = 0;
+  MMD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  MMD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_pcg1_multi),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  int per = 0;
+  MMD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_pcg1_multi, kThreads, lds));
+  return per * cus;
+}
+
+void pcg1_multi(std::vector<Pcg1Req>& reqs, Pcg1Req* h_reqs, Pcg1Req* d_reqs, hipStream_t s) {
+  if (reqs.empty()) return;
+  int off = 0;
+  size_t lds = 0;
+  for (auto& q : reqs) {
+    q.off = off;
+    off += (q.nblk + 7) / 8 * 8;  // whole XCD rounds per request
+    lds = std::max(lds, q.lds);
+  }
+  for (size_t i = 0; i < reqs.size(); ++i) h_reqs[i] = reqs[i];
+  MMD_HIP(hipMemcpyAsync(d_reqs, h_reqs, sizeof(Pcg1Req) * reqs.size(), hipMemcpyHostToDevice, s));
+  for (auto& q : reqs) MMD_HIP(hipMemsetAsync(q.a.bar, 0, sizeof(unsigned), s));
+  int nreq = static_cast<int>(reqs.size());
+  void* args[] = {&d_reqs, &nreq};
+  MMD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_pcg1_multi),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  MMD_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_pcg1_multi), dim3(off),
+                                     dim3(kThreads), args, static_cast<unsigned>(lds), s));
+}
+
 void pcg1(Pcg1Args a, hipStream_t s, const Pcg1Plan* plan) {
   MMD_HIP(hipMemsetAsync(a.bar, 0, sizeof(unsigned), s));
   void* args[] = {&a};
@@ -788,7 +880,7 @@ void pcg1(Pcg1Args a, hipStream_t s, const Pcg1Plan* plan) {
                                      dim3(kThreads), args, 0, s));
 }
 
-void pcg1_plan(const CsrView& A, const std::vector<int>& rp, Pcg1Plan& plan) {
+void pcg1_plan(const CsrView& A, const std::vector<int>& rp, Pcg1Plan& plan, int grid_cap) {
   plan.resident = false;
   const int n = A.n_rows;
   if (n == 0 || (int)rp.size() != n + 1) return;
@@ -798,7 +890,7 @@ void pcg1_plan(const CsrView& A, const std::vector<int>& rp, Pcg1Plan& plan) {
   // with the block count, the per-thread row count with fewer blocks); a
   // matrix whose slices do not fit that many blocks' LDS takes the fewest
   // blocks (multiple of 8) that hold it, up to what can be co-resident
-  int grid0 = 112;
+  int grid0 = grid_cap;
   if (const char* e = std::getenv("MMDEIG_RES_BLOCKS")) grid0 = std::max(8, std::atoi(e));
   grid0 = std::max(8, grid0 / 8 * 8);
   grid0 = std::min(grid0, std::max(8, (n + 63) / 64 / 8 * 8));
@@ -807,7 +899,9 @@ void pcg1_plan(const CsrView& A, const std::vector<int>& rp, Pcg1Plan& plan) {
   int maxsh = 0, cus = 0;
   MMD_HIP(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   MMD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  const size_t static_lds = sizeof(double) * (kThreads / kWave);
+  // room for the static LDS of every kernel that may run the plan (the
+  // batched kernel holds the reduction arrays of all three bodies)
+  const size_t static_lds = 1024;
   const bool edge = A.diag != nullptr;
   const double tot = static_cast<double>(rp[n]) + n;
   std::vector<int> part;
@@ -834,7 +928,9 @@ void pcg1_plan(const CsrView& A, const std::vector<int>& rp, Pcg1Plan& plan) {
       lds = std::max(lds, b);
       max_rows = std::max(max_rows, nr);
     }
-    if (max_rows <= kMaxU * kThreads && lds + static_lds <= static_cast<size_t>(maxsh)) break;
+    if (max_rows <= kMaxU * kThreads &&
+        (lds + 255) / 256 * 256 + static_lds <= static_cast<size_t>(maxsh))
+      break;
   }
   lds = (lds + 255) / 256 * 256;
   MMD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_cg1_res),
@@ -862,7 +958,7 @@ void pcg1_plan_flex(const CsrView& A, const std::vector<int>& rpa, const CsrView
   int maxsh = 0, cus = 0;
   MMD_HIP(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   MMD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  const size_t avail = static_cast<size_t>(maxsh) - sizeof(double) * (kThreads / kWave) - 256;
+  const size_t avail = static_cast<size_t>(maxsh) - 1024 - 256;
   const double tot_bytes = 12.0 * (rpa[n] + rpm[n]) + 8.0 * n;
   const int max_rows = kMaxU2 * kSlots;
   int grid = std::max(16, (n + max_rows - 1) / max_rows);

@@ -16,6 +16,7 @@
 #include <limits>
 #include <numeric>
 
+#include "batch.h"
 #include "dense.h"
 #include "mixed.h"
 #include "pcg_persistent.h"
@@ -419,7 +420,7 @@ bool Solver::pcg_single(int k, const double* B, double* X, double tol, bool use_
       sync();
       it = plans_.emplace(k, Pcg1Plan()).first;
       if (k == 0) {
-        pcg1_plan(a.A, rp, it->second);
+        pcg1_plan(a.A, rp, it->second, batcher_ ? 32 : 112);
       } else {
         std::vector<int> rpm(n + 1);
         d2h(rpm.data(), a.M.rowptr, n + 1);
@@ -429,17 +430,17 @@ bool Solver::pcg_single(int k, const double* B, double* X, double tol, bool use_
     }
     plan = &it->second;
   }
-  {
-    // inside a batch, at most one persistent kernel is in flight on the
-    // device: its grid barrier then only ever waits for workgroups held back
-    // by finite kernels of other streams, never by another barrier
-    std::unique_lock<std::mutex> g(coop_mutex(), std::defer_lock);
-    if (serialize_coop_) g.lock();
-    pcg1(a, s_, plan);
-    hi_.ensure(4);
-    d2h(hi_.p, a.out, 3);
+  if (batcher_) {
+    // the right-hand side is complete before the batched launch reads it;
+    // the batcher returns after that launch has finished
     sync();
+    batcher_->solve(pcg1_request(a, plan));
+  } else {
+    pcg1(a, s_, plan);
   }
+  hi_.ensure(4);
+  d2h(hi_.p, a.out, 3);
+  sync();
   MMD_REQUIRE(hi_.p[2] != 1, MMD_ENOTSPD, "PCG curvature p^T A p <= 0");
   MMD_REQUIRE(hi_.p[2] != 2, MMD_ENOCONV, "PCG reached the iteration cap");
   if (st_ && k > 0) st_->cg_M_iters[k] += hi_.p[1];
@@ -622,6 +623,13 @@ void Solver::cg_mixed(const double* B, int ldb, double* X, int ldx, int b, doubl
     }
   }
   std::vector<double> xx;
+  // a column whose FP64 residual has not halved over the last kStall outer
+  // steps while still above the tolerance is beyond what the FP32 inner solve
+  // can resolve (rounding at the FP32 level of components the deflation does
+  // not remove): the refinement hands all remaining columns to FP64 CG
+  constexpr int kStall = 4;
+  std::vector<std::vector<double>> hist(b);
+  bool fallback = false;
   for (int outer = 0;; ++outer) {
     applyA(0, X, ldx, R, b, b);
     rsub(B, ldb, R, b, n, b, s_);
@@ -632,15 +640,27 @@ void Solver::cg_mixed(const double* B, int ldb, double* X, int ldx, int b, doubl
       if (!live[c]) continue;
       const double floor = 64.0 * 2.2e-16 * norm_a0_ * std::sqrt(xx[c]);
       const bool stalled = outer > 0 && rr[c] > 0.25 * prev[c] && rr[c] <= floor * floor;
-      if (!(bn2[c] > 0.0) || rr[c] <= tol * tol * bn2[c] || stalled)
+      if (!(bn2[c] > 0.0) || rr[c] <= tol * tol * bn2[c] || stalled) {
         live[c] = 0;
-      else
+      } else {
         act.push_back(c);
+        hist[c].push_back(rr[c]);
+        const size_t h = hist[c].size();
+        if (h > kStall && hist[c][h - 1] > 0.25 * hist[c][h - 1 - kStall]) fallback = true;
+      }
       prev[c] = rr[c];
     }
     if (act.empty()) break;
-    MMD_REQUIRE(outer < max_outer, MMD_ENOCONV,
-                "mixed-precision refinement did not reach the tolerance");
+    if (fallback || outer >= max_outer) {
+      std::vector<int> its64;
+      cg(0, OpKind::A, B, ldb, X, ldx, n, b, tol, true, nullptr, 0, "mxfb", &its64);
+      for (int c = 0; c < b; ++c) total[c] += its64[c];
+      if (st_) st_->mixed_fallbacks += 1;
+      if (log_on())
+        std::fprintf(stderr, "[mmdeig] mixed refinement: FP64 CG finishes %d of %d columns\n",
+                     static_cast<int>(act.size()), b);
+      break;
+    }
     if (dfl && dfl->m > 0) {
       // C = Q^T R ; R -= Q C ; X += Q diag(mu) C   (all FP64)
       const int mq = dfl->m;

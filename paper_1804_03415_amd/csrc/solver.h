@@ -11,6 +11,8 @@
 
 namespace mmd {
 
+class OpBatcher;
+
 // Device scratch owned by one solver call, reused across phases by name.
 class Pool {
  public:
@@ -42,12 +44,10 @@ class Solver {
   // cooperative persistent ones (needed when other streams run concurrently:
   // a grid barrier must never wait on workgroups that cannot be resident)
   void set_persistent(bool on) { use_persistent_ = on; }
-  // serialise the persistent kernels of concurrent solvers (see pcg_single)
-  void set_serialize_persistent(bool on) { serialize_coop_ = on; }
-  static std::mutex& coop_mutex() {
-    static std::mutex m;
-    return m;
-  }
+  // inside a batch: single-vector operator solves go through the batcher
+  // (one cooperative launch for the solves pending across the batch), and
+  // level-0 resident plans use few blocks so several solves fit at once
+  void set_batcher(OpBatcher* b) { batcher_ = b; }
 
   // building blocks exposed through mmd_apply / mmd_solve
   void apply_op(int level, int op, const double* X, double* Y, int b);
@@ -152,7 +152,7 @@ class Solver {
   HBuf<int> hi_;
   int inner_iters_ = 16;
   bool use_persistent_ = true;
-  bool serialize_coop_ = false;
+  OpBatcher* batcher_ = nullptr;
   std::map<int, Pcg1Plan> plans_;  // resident plain-CG plan per level (level 0)
   double norm_a0_ = 0.0;           // ||A||_inf of level 0 (mixed-precision floor test)
   std::vector<double> tpcg_;       // relative PCG tolerance per level (k >= 1)

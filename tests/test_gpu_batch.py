@@ -59,3 +59,22 @@ def test_batched_reports_bad_member(batch):
     assert "problem 2" in str(e.value)
     with pytest.raises(MMDError):
         eig_leftmost_batched([decs[0], decs[0]], [5, 5], tol=1e-10)
+
+
+def test_operator_solves_are_merged(batch, capfd, monkeypatch):
+    """With several problems in flight, their single-vector operator solves
+    share cooperative launches of the batched persistent kernel: fewer
+    launches than solves (counts from the MMDEIG_LOG line of the batch)."""
+    import re
+    from paper_1804_03415_amd import eig_leftmost_batched
+    probs, decs = batch
+    monkeypatch.setenv("MMDEIG_LOG", "1")
+    capfd.readouterr()
+    out = eig_leftmost_batched(decs, [nev for _, nev, _ in probs], tol=1e-10, streams=6)
+    err = capfd.readouterr().err
+    m = re.search(r"batch: (\d+) operator solves in (\d+) batched launches", err)
+    assert m, err[-2000:]
+    solves, launches = int(m.group(1)), int(m.group(2))
+    assert solves > 0 and launches < solves
+    for (p, nev, kw), (lam, V, st) in zip(probs, out):
+        assert dense.rel_residuals(p.scipy(), lam, V.cpu().numpy().T).max() < 1e-8
