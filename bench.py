@@ -54,13 +54,17 @@ def parse():
                     help="HBM bytes per launch of the dominant kernel from rocprofv3 counters")
     ap.add_argument("--verbose", type=int, default=0)
     ap.add_argument("--workload", default="rgg",
-                    choices=["rgg", "knn-backward", "rgg-batch", "gram"],
+                    choices=["rgg", "knn-backward", "rgg-batch", "gram", "swissroll"],
                     help="rgg: the leftmost-300 eigensolve of the n = 1e5 RGG (default); "
                          "knn-backward: forward (20 pairs) and eigen-backward of the "
                          "n = 2e5 kNN-GMM graph; rgg-batch: 100 pairs of each of a batch "
                          "of RGGs with sizes uniform in [5000, 50000]; gram: the FP64 MFMA "
                          "Gram X^T Y and projection X C products at the 64^3 diffusion "
-                         "refinement shape (n = 262144, 500 columns)")
+                         "refinement shape (n = 262144, 500 columns); swissroll: the paper's "
+                         "SwissRoll graph (n = 20000) with its decomposition parameters")
+    ap.add_argument("--swiss-levels", type=int, default=3, choices=[3, 4],
+                    help="swissroll: the paper's 3-level (eta 0.1) or 4-level (eta 0.2) "
+                         "decomposition")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--streams", type=int, default=8)
     ap.add_argument("--batch-sequential", type=int, default=0,
@@ -288,6 +292,88 @@ def rgg_batch(a):
     print(json.dumps(res), flush=True)
 
 
+def level_table(st):
+    """Per-level counters in the paper's statistics schema (Section 7.4 tables):
+    refinement (#I, #O), #Iter, #cg(B), mean #(B), extension (#I, #O), #pcg(A),
+    mean #(A), mean inner #(M) per outer PCG iteration, Lanczos steps."""
+    rows = {}
+    for k, v in sorted(st["levels"].items(), key=lambda kv: -int(kv[0])):
+        calls_a = max(v["pcg_A_calls"], 1)
+        rows[int(k)] = {
+            "refine_in_out": [v["ref_in"], v["ref_out"]], "refine_iter": v["ref_iter"],
+            "cg_B_calls": v["cg_B_calls"],
+            "mean_B": round(v["cg_B_iters"] / max(v["cg_B_calls"], 1), 2),
+            "extend_in_out": [v["ext_in"], v["ext_out"]], "pcg_A_calls": v["pcg_A_calls"],
+            "mean_A": round(v["pcg_A_iters"] / calls_a, 2),
+            "mean_M_per_A": round(v["cg_M_iters"] / max(v["pcg_A_iters"], 1), 2),
+            "lanczos_steps": v["lanczos_steps"], "seconds": round(v["seconds_level"], 3)}
+    return rows
+
+
+def swissroll_run(a):
+    """The paper's SwissRoll data set (n = 20000, kNN k = 10, Section 7.1) with
+    its decompositions (K, eps_1, eta, c) = (3, 1e-5, 0.1, 20) or
+    (4, 1e-5, 0.2, 20), 300 smallest pairs: the paper's own output (Alg. 6
+    stopped at level 1, accuracy eps_1), the solve continued to level 0 at
+    tol, and restarted Lanczos on A^-1 without the hierarchy (IRLM-CG, the
+    paper's comparison method) at the same tol."""
+    import torch
+    import workloads
+    from paper_1804_03415_amd import Decomposition
+    nev = a.nev
+    K = a.swiss_levels
+    eta = 0.1 if K == 3 else 0.2
+    p = workloads.swissroll(20000, seed=0)
+    A = p.scipy()
+    t = time.perf_counter()
+    dec = Decomposition.from_problem(p, levels=K, eps1=1e-5, eta=eta, cbound=20.0, r_hops=5)
+    t_build = time.perf_counter() - t
+    info = dec.info()
+    print("swissroll: n %d nnz %d, levels %s, eps %s, build %.1f s" % (
+        p.n, p.nnz, info["sizes"], ["%.3g" % e for e in info["eps"]], t_build),
+        file=sys.stderr, flush=True)
+
+    def run(d, **kw):
+        for _ in range(a.warmup):
+            d.eig_leftmost(nev, tol=a.tol, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            lam, V, st = d.eig_leftmost(nev, tol=a.tol, **kw)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / a.steps
+        Vh = V.cpu().numpy().T
+        rho = np.linalg.norm(A @ Vh - Vh * lam[None, :], axis=0) / (
+            np.abs(lam) * np.linalg.norm(Vh, axis=0))
+        return lam, el, float(rho.max()), st
+
+    lam1, el1, rho1, st1 = run(dec, stop_level=1)
+    lam0, el0, rho0, st0 = run(dec)
+    # Lemma 3.3 at level 1: |1/lambda_i - mu_i| <= eps_1 against the level-0 solve
+    lemma = float(np.max(np.abs(1.0 / lam1 - 1.0 / lam0)))
+    dk0 = Decomposition.from_problem(p, levels=0)
+    lamk, elk, rhok, stk = run(dk0)
+    dk0.close()
+    res = {"metric": "eigenpairs/s (SwissRoll, n=20000, 300 pairs)",
+           "value": round(nev / el0, 3), "unit": "eigenpairs/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(1000 * el0, 2),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "swissroll_n20000_k10_nev%d_K%d" % (nev, K), "nnz": p.nnz,
+                      "levels": info["sizes"], "eps": info["eps"], "eps1": 1e-5, "eta": eta,
+                      "c": 20.0, "tol": a.tol, "build_s": round(t_build, 2)},
+           "max_rel_residual": rho0, "residual_ok": bool(rho0 <= 1e-8),
+           "paper_output_level1": {"seconds": round(el1, 3), "eigenpairs_per_s": round(nev / el1, 3),
+                                   "max_abs_mu_error_vs_level0": lemma, "eps_1": info["eps"][1],
+                                   "levels": level_table(st1)},
+           "solve_to_level0": {"seconds": round(el0, 3), "levels": level_table(st0)},
+           "no_hierarchy_irlm_cg": {"seconds": round(elk, 3), "eigenpairs_per_s": round(nev / elk, 3),
+                                    "max_rel_residual": rhok,
+                                    "max_rel_eig_diff": float(np.max(np.abs(lamk - lam0) / lam0))}}
+    dec.close()
+    print(json.dumps(res), flush=True)
+
+
 def gram_products(a):
     """TFLOP/s of the FP64 MFMA tall-skinny products (mmdk_gram, mmdk_gemm) at
     the refinement block shape of the 500-pair 64^3 diffusion solve, against
@@ -355,6 +441,8 @@ def main():
         return rgg_batch(a)
     if a.workload == "gram":
         return gram_products(a)
+    if a.workload == "swissroll":
+        return swissroll_run(a)
     p = workloads.rgg(a.n, 0)
     t = time.perf_counter()
     dec = Decomposition.from_problem(p, levels=a.levels, targets=(4, 8))

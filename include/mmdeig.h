@@ -68,6 +68,17 @@ typedef struct {
   int32_t r_hops;          /* localisation radius of Psi in patch hops [1]       */
   int64_t exact_max_n;     /* levels whose fine size <= this use the exact Psi [0] */
   int32_t min_coarse;      /* stop coarsening below this many dofs [4]           */
+  int32_t max_patch;       /* eps1 > 0: largest patch [32]                       */
+  double eps1;             /* > 0: graphs are partitioned to prescribed accuracy
+                              (Section 2.3): eps(P^(k)) <= eps1 / eta^(k-1) and
+                              eps(P) delta(P) <= cbound, instead of targets.
+                              Patches grow from Morton-ordered seeds, trying
+                              the adjacent vertex of largest total coupling
+                              sum |a_vp| first; the localised Psi then needs a
+                              radius r_hops that keeps the level accurate to
+                              eps_k (5 on the SwissRoll graph of Section 7.1) [0] */
+  double eta;              /* ratio eps_k / eps_(k+1) [0.1]                      */
+  double cbound;           /* condition bound c [20]                             */
 } mmd_build_opts;
 
 /* Solver options (Section 5 parameter choice).  Zero fields take defaults. */

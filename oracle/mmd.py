@@ -147,6 +147,72 @@ def greedy_partition(A: sp.csr_matrix, coords: Optional[np.ndarray], target: int
     return out
 
 
+def eps_partition(A: sp.csr_matrix, coords: Optional[np.ndarray], eps_k: float, cbound: float,
+                  closed: bool, max_size: int = 32):
+    """Partition with prescribed accuracy (Section 2.3: the partition must give
+    error factor eps(P) <= eps_k and eps(P) delta(P) <= c; reading of the
+    deferred partitioner).
+
+    Seeds in Morton order (vertex order without coordinates).  A seed opens a
+    patch that grows greedily: among the unassigned vertices adjacent to the
+    patch and not yet refused by it, the one with the largest total coupling
+    sum_{p in P} |a_vp| to the patch is tried next (ties: smaller vertex id).
+    It joins when the enlarged patch still has eps(P) = 1 / lambda_2(E_P) <=
+    eps_k (E_P the interior energy on level 1, the closed energy above) and
+    eps(P) delta(P) <= c with delta(P) = 1 / (phi^T Abar_P^-1 phi), phi the
+    unit eigenvector of lambda_1(E_P) and Abar_P the closed energy (principal
+    submatrix); otherwise the patch refuses it.  The patch closes when no
+    candidate is left or it holds max_size vertices.  Members sorted; patches
+    in creation order.
+    """
+    n = A.shape[0]
+    order = morton_order(coords) if coords is not None else np.arange(n)
+    indptr, indices, data = A.indptr, A.indices, A.data
+    pid = np.full(n, -1, dtype=np.int64)
+    patches = []
+    for s0 in order:
+        s0 = int(s0)
+        if pid[s0] >= 0:
+            continue
+        cur = len(patches)
+        members = [s0]
+        pid[s0] = cur
+        coupling = {}           # candidate -> total coupling to the patch
+        refused = set()
+
+        def add_couplings(v):
+            for a in range(indptr[v], indptr[v + 1]):
+                u = int(indices[a])
+                if u != v and pid[u] < 0:
+                    coupling[u] = coupling.get(u, 0.0) + abs(float(data[a]))
+
+        add_couplings(s0)
+        while len(members) < max_size:
+            cands = [(-w, u) for u, w in coupling.items() if u not in refused and pid[u] < 0]
+            if not cands:
+                break
+            u = min(cands)[1]
+            cand = np.sort(np.asarray(members + [u], dtype=np.int64))
+            Abar = A[cand][:, cand].toarray()  # closed energy: principal submatrix
+            E = Abar if closed else interior_energy(A, cand)
+            w, V = np.linalg.eigh(0.5 * (E + E.T))
+            ok = False
+            if w[1] > 0:
+                eps = 1.0 / w[1]
+                phi = V[:, 0]
+                delta = 1.0 / float(phi @ np.linalg.solve(Abar, phi))
+                ok = eps <= eps_k and eps * delta <= cbound
+            if ok:
+                members.append(u)
+                pid[u] = cur
+                del coupling[u]
+                add_couplings(u)
+            else:
+                refused.add(u)
+        patches.append(np.sort(np.asarray(members, dtype=np.int64)))
+    return patches
+
+
 def patch_id_of(patches, n):
     pid = np.empty(n, dtype=np.int64)
     for j, m in enumerate(patches):
@@ -205,14 +271,24 @@ def local_basis(A: sp.csr_matrix, members, closed=False):
 
 
 def householder_vector(phi):
-    """u with H = I - 2 u u^T / u^T u mapping e_1 to -sign(phi_1) phi.
+    """(u, t): H = I - 2 u u^T / u^T u maps e_t to -sign(phi_t) phi, with the
+    pivot slot t the first i with |phi_i| >= (1 - 1e-8) max_j |phi_j|.
 
-    u = phi + s e_1, s = +1 if phi_1 >= 0 else -1 (no cancellation).
+    u = phi + s e_t, s = +1 if phi_t >= 0 else -1 (no cancellation).  The
+    complement U of phi in the patch is the columns H e_i, i != t, in
+    ascending slot order (Lemma 2.3 remark: any orthonormal completion).  A
+    pivot of near-maximal magnitude keeps the sign choice, and with it U, away
+    from entries that rounding alone decides (an eigenvector entry that is
+    zero in exact arithmetic); taking the first of the near-maximal entries
+    keeps the choice stable when symmetry makes several maxima equal in exact
+    arithmetic.
     """
+    a = np.abs(phi)
+    t = int(np.nonzero(a >= (1.0 - 1e-8) * a.max())[0][0])
     u = phi.copy()
-    s = 1.0 if phi[0] >= 0 else -1.0
-    u[0] += s
-    return u
+    s = 1.0 if phi[t] >= 0 else -1.0
+    u[t] += s
+    return u, t
 
 
 def psi_exact(A: sp.csr_matrix, patches, phis):
@@ -301,7 +377,7 @@ class Level:
     Psi: Optional[sp.csr_matrix] = None    # N_{k-1} x N_k
     patches: list = field(default_factory=list)
     phis: list = field(default_factory=list)
-    hh: list = field(default_factory=list)
+    hh: list = field(default_factory=list)   # (u, pivot slot) per patch
     eps_patch: Optional[np.ndarray] = None
     eps_level: float = 0.0                 # eps(P^(k))
     lam_max_M: float = 1.0                 # Gershgorin bound on lambda_max(M^(k))
@@ -315,28 +391,30 @@ class Level:
         return sum(len(m) - 1 for m in self.patches)
 
     def U_apply(self, y: np.ndarray) -> np.ndarray:
-        """x = U y: per patch insert 0 in slot 1 and apply H_j."""
+        """x = U y: per patch place y's slots in the non-pivot slots (ascending),
+        0 in the pivot slot, and apply H_j."""
         y = np.asarray(y)
         nfine = sum(len(m) for m in self.patches)
         x = np.zeros((nfine,) + y.shape[1:])
         off = 0
-        for mem, u in zip(self.patches, self.hh):
+        for mem, (u, t) in zip(self.patches, self.hh):
             p = len(mem)
+            rest = [i for i in range(p) if i != t]
             z = np.zeros((p,) + y.shape[1:])
-            z[1:] = y[off:off + p - 1]
+            z[rest] = y[off:off + p - 1]
             off += p - 1
             z = z - (2.0 / (u @ u)) * np.multiply.outer(u, u @ z)
             x[mem] = z
         return x
 
     def Ut_apply(self, x: np.ndarray) -> np.ndarray:
-        """y = U^T x: per patch apply H_j to x_P and drop slot 1."""
+        """y = U^T x: per patch apply H_j to x_P and keep the non-pivot slots."""
         x = np.asarray(x)
         out = []
-        for mem, u in zip(self.patches, self.hh):
+        for mem, (u, t) in zip(self.patches, self.hh):
             z = x[mem]
             z = z - (2.0 / (u @ u)) * np.multiply.outer(u, u @ z)
-            out.append(z[1:])
+            out.append(np.delete(z, t, axis=0))
         return np.concatenate(out) if out else np.zeros((0,) + x.shape[1:])
 
 
@@ -357,7 +435,8 @@ def gershgorin_max(M: Optional[sp.csr_matrix]) -> float:
 
 
 def build_mmd(A, coords=None, grid=None, levels=3, targets=(4, 8), grid_blocks=(4, 2),
-              r_hops=1, exact_max_n=0, min_coarse=4):
+              r_hops=1, exact_max_n=0, min_coarse=4, eps1=0.0, eta=0.1, cbound=20.0,
+              max_patch=32):
     """Build the K-level decomposition.
 
     levels      number of coarse levels K (stops early when a level would not
@@ -366,6 +445,10 @@ def build_mmd(A, coords=None, grid=None, levels=3, targets=(4, 8), grid_blocks=(
     grid_blocks tensor block edge per level for structured grids (last repeats)
     r_hops      localisation radius of Psi in patch hops
     exact_max_n levels with N_{k-1} <= exact_max_n use the exact Psi
+    eps1, eta, cbound, max_patch
+                eps1 > 0: graphs are partitioned to prescribed accuracy,
+                eps(P^(k)) <= eps1 / eta^(k-1) and eps delta <= cbound
+                (Section 2.3), patches of at most max_patch vertices
     """
     A = sp.csr_matrix(A)
     A.sort_indices()
@@ -380,6 +463,10 @@ def build_mmd(A, coords=None, grid=None, levels=3, targets=(4, 8), grid_blocks=(
         if prev.grid is not None:
             blk = grid_blocks[min(k - 1, len(grid_blocks) - 1)]
             patches, cgrid = grid_partition(prev.grid, blk)
+        elif eps1 > 0:
+            patches = eps_partition(Ak, prev.coords, eps1 / eta ** (k - 1), cbound, k >= 2,
+                                    max_patch)
+            cgrid = None
         else:
             tgt = targets[min(k - 1, len(targets) - 1)]
             patches = greedy_partition(Ak, prev.coords, tgt)
@@ -396,6 +483,9 @@ def build_mmd(A, coords=None, grid=None, levels=3, targets=(4, 8), grid_blocks=(
             Psi = psi_exact(Ak, patches, phis)
         else:
             Psi = psi_localized(Ak, patches, phis, r_hops)
+        # the support of psi_j is the set of its nonzero entries: a stored exact
+        # zero carries no coupling into the Galerkin patterns
+        Psi.eliminate_zeros()
         Anew = galerkin(Psi, Ak)
         Mnew = galerkin(Psi, prev.M)
         ccoords = None

@@ -36,7 +36,9 @@ class mmd_build_opts(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("n_targets", ctypes.c_int32),
                 ("targets", ctypes.c_int32 * 8), ("n_grid_blocks", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32 * 8), ("r_hops", ctypes.c_int32),
-                ("exact_max_n", ctypes.c_int64), ("min_coarse", ctypes.c_int32)]
+                ("exact_max_n", ctypes.c_int64), ("min_coarse", ctypes.c_int32),
+                ("max_patch", ctypes.c_int32), ("eps1", ctypes.c_double),
+                ("eta", ctypes.c_double), ("cbound", ctypes.c_double)]
 
 
 class eig_opts(ctypes.Structure):

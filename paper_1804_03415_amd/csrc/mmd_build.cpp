@@ -207,7 +207,115 @@ std::vector<double> patch_energy(const HostCSR& A, const std::vector<int>& mem, 
   return E;
 }
 
+// Partition with prescribed accuracy (Section 2.3: eps(P) <= eps_k and
+// eps(P) delta(P) <= c).  Seeds in Morton order (vertex order without
+// coordinates); a seed opens a patch that grows greedily: among the unassigned
+// vertices adjacent to the patch and not yet refused by it, the one with the
+// largest total coupling sum_{p in P} |a_vp| to the patch is tried next (ties:
+// smaller vertex id).  It joins when the enlarged patch keeps
+// eps(P) = 1 / lambda_2(E_P) <= eps_k (E_P the patch energy of the level) and
+// eps(P) delta(P) <= c, where delta(P) = 1 / (phi^T Abar_P^-1 phi) with phi
+// the eigenvector of lambda_1(E_P) and Abar_P the principal submatrix;
+// otherwise the patch refuses it.  The patch closes when no candidate is left
+// or it holds max_size vertices.  Couplings accumulate member by member in
+// join order and CSR order within a row.
+Patches eps_patches(const HostCSR& A, const std::vector<double>& xyz, int d, double eps_k,
+                    double cbound, bool closed, int max_size) {
+  const int n = A.n_rows;
+  std::vector<int> order;
+  if (d > 0) order = morton_order(xyz, n, d);
+  else {
+    order.resize(n);
+    std::iota(order.begin(), order.end(), 0);
+  }
+  std::vector<int> pid(n, -1), stamp(n, -1), refused(n, -1);
+  std::vector<double> coup(n, 0.0);
+  Patches P;
+  std::vector<int> cands, cand;
+  for (int s0 : order) {
+    if (pid[s0] >= 0) continue;
+    const int cur = static_cast<int>(P.size());
+    std::vector<int> mem{s0};
+    pid[s0] = cur;
+    cands.clear();
+    auto add_couplings = [&](int v) {
+      for (int64_t k = A.ptr[v]; k < A.ptr[v + 1]; ++k) {
+        const int u = A.col[k];
+        if (u == v || pid[u] >= 0) continue;
+        if (stamp[u] != cur) {
+          stamp[u] = cur;
+          coup[u] = 0.0;
+          cands.push_back(u);
+        }
+        coup[u] += std::fabs(A.val[k]);
+      }
+    };
+    add_couplings(s0);
+    while (static_cast<int>(mem.size()) < max_size) {
+      int u = -1;
+      for (int c : cands) {
+        if (pid[c] >= 0 || refused[c] == cur) continue;
+        if (u < 0 || coup[c] > coup[u] || (coup[c] == coup[u] && c < u)) u = c;
+      }
+      if (u < 0) break;
+      cand = mem;
+      cand.push_back(u);
+      std::sort(cand.begin(), cand.end());
+      const int p = static_cast<int>(cand.size());
+      const std::vector<double> E = patch_energy(A, cand, closed);
+      std::vector<double> w, Z;
+      dense::sym_eig(p, E.data(), w, &Z);
+      bool ok = false;
+      std::vector<double> R;
+      const std::vector<double> Ab = patch_energy(A, cand, true);
+      if (w[1] > 0.0 && dense::cholesky_upper(p, Ab.data(), R)) {
+        const double eps = 1.0 / w[1];
+        // phi^T Abar^-1 phi by Cholesky of the principal submatrix
+        std::vector<double> y(p);
+        for (int i = 0; i < p; ++i) {  // R^T y = phi
+          double t = Z[(size_t)i * p];
+          for (int j = 0; j < i; ++j) t -= R[(size_t)j * p + i] * y[j];
+          y[i] = t / R[(size_t)i * p + i];
+        }
+        double q = 0.0;
+        for (int i = 0; i < p; ++i) q += y[i] * y[i];
+        const double delta = 1.0 / q;
+        ok = eps <= eps_k && eps * delta <= cbound;
+      }
+      if (ok) {
+        mem.push_back(u);
+        pid[u] = cur;
+        add_couplings(u);
+      } else {
+        refused[u] = cur;
+      }
+    }
+    std::sort(mem.begin(), mem.end());
+    P.push_back(std::move(mem));
+  }
+  return P;
+}
+
 // ---------------------------------------------------------------- sparse helpers
+// Remove stored entries that are exactly zero (a basis vector's support is the
+// set of its nonzero entries, so no coupling is derived from a stored zero).
+void drop_zeros(HostCSR& X) {
+  int64_t q = 0;
+  for (int i = 0; i < X.n_rows; ++i) {
+    const int64_t b = X.ptr[i], e = X.ptr[i + 1];
+    X.ptr[i] = q;
+    for (int64_t k = b; k < e; ++k)
+      if (X.val[k] != 0.0) {
+        X.col[q] = X.col[k];
+        X.val[q] = X.val[k];
+        ++q;
+      }
+  }
+  X.ptr[X.n_rows] = q;
+  X.col.resize(q);
+  X.val.resize(q);
+}
+
 HostCSR transpose(const HostCSR& X) {
   HostCSR T;
   T.n_rows = X.n_cols;
@@ -735,6 +843,11 @@ void build_hierarchy(mmd_handle& h, const mmd_csr& in, const mmd_build_opts& o) 
     if (!prev.grid.empty()) {
       const int blk = blocks[std::min<size_t>(k - 1, blocks.size() - 1)];
       P = grid_patches(prev.grid, blk, cgrid);
+    } else if (o.eps1 > 0) {
+      const double eta = o.eta > 0 ? o.eta : 0.1;
+      const double cb = o.cbound > 0 ? o.cbound : 20.0;
+      const int mx = o.max_patch > 0 ? o.max_patch : 32;
+      P = eps_patches(Ak, prev.coords, prev.cdim, o.eps1 / std::pow(eta, k - 1), cb, k >= 2, mx);
     } else {
       const int tgt = targets[std::min<size_t>(k - 1, targets.size() - 1)];
       P = greedy_patches(Ak, prev.coords, prev.cdim, tgt);
@@ -779,12 +892,28 @@ void build_hierarchy(mmd_handle& h, const mmd_csr& in, const mmd_build_opts& o) 
         for (int i = 0; i < p; ++i) L.phi[off + i] = sg * Z[(size_t)i * p];
         L.eps_patch[j] = w[1] > 0 ? 1.0 / w[1] : std::numeric_limits<double>::infinity();
       }
+      // Householder pivot: the first i with |phi_i| >= (1 - 1e-8) max |phi|,
+      // so the sign choice never rests on an entry that is zero up to
+      // rounding, and maxima that symmetry makes equal do not let rounding
+      // pick among them.  Slot order of the transfer: the pivot first, then
+      // the other members ascending; phi keeps the ascending member order.
+      double amax = 0.0;
+      for (int i = 0; i < p; ++i) amax = std::max(amax, std::fabs(L.phi[off + i]));
+      int t = 0;
+      while (t < p - 1 && !(std::fabs(L.phi[off + t]) >= (1.0 - 1e-8) * amax)) ++t;
+      const double s_piv = L.phi[off + t] >= 0 ? 1.0 : -1.0;
       double uu = 0.0;
       for (int i = 0; i < p; ++i) {
-        double u = L.phi[off + i];
-        if (i == 0) u += L.phi[off] >= 0 ? 1.0 : -1.0;
-        L.hh_u[off + i] = u;
+        const double u = L.phi[off + i] + (i == t ? s_piv : 0.0);
         uu += u * u;
+      }
+      L.members[off] = P[j][t];
+      L.hh_u[off] = L.phi[off + t] + s_piv;
+      for (int i = 0, q = 1; i < p; ++i) {
+        if (i == t) continue;
+        L.members[off + q] = P[j][i];
+        L.hh_u[off + q] = L.phi[off + i];
+        ++q;
       }
       L.hh_scale[j] = 2.0 / uu;
     }
@@ -794,6 +923,7 @@ void build_hierarchy(mmd_handle& h, const mmd_csr& in, const mmd_build_opts& o) 
       L.Psi = psi_exact(Ak, P, L.phi, L.patch_ptr);
     else
       L.Psi = psi_localized(Ak, P, L.phi, L.patch_ptr, r_hops);
+    drop_zeros(L.Psi);
     L.A = galerkin(L.Psi, &Ak);
     L.M = galerkin(L.Psi, k == 1 ? nullptr : &prev.M);
     L.lam_max_M = gershgorin(L.M);

@@ -73,6 +73,9 @@ CASES = {
     "rgg_2000": (lambda: wl.rgg(2000, 0), dict(levels=3)),
     "knn_1500": (lambda: wl.knn_gmm(1500, 10, 1), dict(levels=2)),
     "grid3d_8": (lambda: wl.grid3d_lognormal(8, 0), dict(levels=2, grid_blocks=(2, 2))),
+    # partition to prescribed accuracy (eps_1, eta, c) on the SwissRoll graph
+    "swissroll_3000": (lambda: wl.swissroll(3000, seed=2), dict(levels=2, eps1=1e-5, eta=0.1,
+                                                                cbound=20.0, r_hops=5)),
 }
 
 
@@ -99,7 +102,15 @@ def test_build_parity(built):
             rp, ci, v, shape = dec.export(k, which)
             X = sp.csr_matrix((v, ci, rp), shape=shape)
             assert X.shape == ref.shape
-            assert X.nnz == ref.nnz
+            # same stored pattern, except entries that are zero in exact
+            # arithmetic and come out as rounding noise on one side only (the
+            # coarse SwissRoll basis has 27 such in 17413); the value check
+            # below holds every one-sided entry to 1e-11 max|ref|
+            Xs = sp.csr_matrix((np.ones(X.nnz), X.indices, X.indptr), shape=shape)
+            Rs = sp.csr_matrix((np.ones(ref.nnz), ref.indices, ref.indptr), shape=shape)
+            only = (Xs - Rs).tocsr()
+            only.eliminate_zeros()
+            assert only.nnz <= 1e-2 * ref.nnz
             assert abs(X - ref).max() <= 1e-11 * abs(ref).max()
 
 
@@ -541,6 +552,40 @@ def test_coarse_level_approximation(torch_cuda, case):
             assert np.max(np.abs(mu - 1.0 / w[:nev])) <= 1.1 * eps_k
             R = Ainv @ Vh - Vh / w[None, :nev]
             assert np.max(np.linalg.norm(R, axis=0)) <= 2.2 * eps_k
+
+
+def test_swissroll_prescribed_accuracy(torch_cuda):
+    """SwissRoll graph (Section 7.1, 2000 points at the full roll's density)
+    decomposed with the paper's (eps_1, eta, c) = (1e-5, 0.1, 20): the level
+    sizes match the oracle's, the full solve (Alg. 6 continued to level 0)
+    matches the oracle pair by pair, and the paper's own output (stop at
+    level 1) meets Lemma 3.3, |mu_i - mu_i(A^-1)| <= eps_1, against the dense
+    spectrum, and matches the oracle's coarse mode."""
+    from paper_1804_03415_amd import Decomposition
+    p = wl.swissroll(2000, seed=2)
+    kw = dict(levels=2, eps1=1e-5, eta=0.1, cbound=20.0, r_hops=5)
+    A = p.scipy()
+    dec = Decomposition.from_problem(p, **kw)
+    info = dec.info()
+    Mo = mm.build_mmd(A, coords=p.coords, **kw)
+    assert info["sizes"] == [lev.n for lev in Mo.levels]
+    w = np.linalg.eigvalsh(A.toarray())
+    nev = 20
+    lam, V, st = dec.eig_leftmost(nev, tol=1e-10)
+    lo, Vo = krylov.eig_leftmost(A, nev, 1e-10, mmd=Mo)
+    assert np.max(np.abs(lam - lo) / lo) < 1e-10
+    assert np.max(np.abs(lam - w[:nev]) / w[:nev]) < 1e-9
+    Vh = V.cpu().numpy().T
+    ang, cl = dense.cluster_angles(lo, Vo, Vh)
+    assert ang.max() < 1e-7
+    assert dense.rel_residuals(A, lam, Vh).max() < 1e-8
+    lam1, V1, _ = dec.eig_leftmost(nev, tol=1e-10, stop_level=1)
+    lo1, _ = krylov.eig_leftmost(A, nev, 1e-10, mmd=Mo, stop_level=1)
+    eps1 = info["eps"][1]
+    assert eps1 <= 1e-5
+    assert np.max(np.abs(1.0 / lam1 - 1.0 / w[:nev])) <= eps1
+    assert np.max(np.abs(1.0 / lam1 - 1.0 / lo1)) <= 0.5 * eps1
+    dec.close()
 
 
 # ------------------------------------------------------------------- FP64 MFMA products (a8)

@@ -88,14 +88,31 @@ def test_partitions_cover_exactly_once():
 
 
 def test_householder_complement():
+    """H_j is orthogonal, its pivot column is +-phi, the other columns span
+    phi's complement; the pivot is the largest-magnitude entry, also when the
+    first entry is zero or at rounding level."""
     rng = np.random.default_rng(0)
-    for sgn in (1, -1):
-        phi = rng.standard_normal(9); phi /= np.linalg.norm(phi); phi[0] = sgn * abs(phi[0])
-        u = mm.householder_vector(phi)
+    for case in range(4):
+        phi = rng.standard_normal(9)
+        if case == 2:
+            phi[0] = 0.0
+        if case == 3:
+            phi[0] = 1e-300
+        phi /= np.linalg.norm(phi)
+        if case == 1:
+            phi = -phi
+        u, t = mm.householder_vector(phi)
+        assert t == int(np.argmax(np.abs(phi)))  # distinct magnitudes here
         H = np.eye(9) - 2 * np.outer(u, u) / (u @ u)
         assert np.allclose(H @ H.T, np.eye(9), atol=1e-14)
-        assert np.allclose(np.abs(H[:, 0]), np.abs(phi), atol=1e-14)
-        assert np.allclose(H[:, 1:].T @ phi, 0, atol=1e-14)
+        assert np.allclose(H[:, t], -np.sign(phi[t]) * phi, atol=1e-14)
+        rest = [i for i in range(9) if i != t]
+        assert np.allclose(H[:, rest].T @ phi, 0, atol=1e-14)
+    # maxima equal in exact arithmetic but not after rounding: the first one
+    phi = np.array([0.1, 0.5, 0.5 * (1 + 1e-15), 0.5 * (1 - 1e-15), 0.2])
+    phi /= np.linalg.norm(phi)
+    assert mm.householder_vector(phi)[1] == 1
+    assert mm.householder_vector(phi[::-1].copy())[1] == 1
 
 
 # --------------------------------------------------------------------------- MMD invariants
@@ -550,3 +567,73 @@ def test_shift_cluster_reference():
     wd = np.linalg.eigvalsh(A.toarray())[:ref.size]
     assert ref.size == dense.component_count(A) == 19
     assert np.max(np.abs(wd - ref)) <= 4 * 2.0 ** -52 * float(abs(A).sum(axis=1).max())
+
+
+# --------------------------------------------------------------------------- prescribed-accuracy partition
+def test_eps_partition_meets_its_bounds():
+    """SwissRoll graph (Section 7.1, a 1500-point sample at the full roll's
+    point density) partitioned to prescribed accuracy with the paper's
+    (eps_1, eta, c) = (1e-5, 0.1, 20): every patch of every level satisfies
+    eps(P) <= eps_k and eps(P) delta(P) <= c, recomputed here from the
+    definitions (Section 2.2: eps = 1 / lambda_2 of the patch energy,
+    delta = 1 / (phi^T Abar^-1 phi)), the patches cover each level exactly
+    once, the levels coarsen, and M^(k) >= I (Lemma 4.3; the localized Psi
+    keeps Phi^T Psi = I)."""
+    p = wl.swissroll(1500, seed=2)
+    A = p.scipy()
+    # unit self-loops: A 1 = 1 on a connected graph, lambda_1 = 1
+    assert np.allclose(A @ np.ones(p.n), 1.0, rtol=0, atol=1e-6 * abs(A).max())
+    M = mm.build_mmd(A, coords=p.coords, levels=2, eps1=1e-5, eta=0.1, cbound=20.0, r_hops=2)
+    assert M.K == 2
+    for k in (1, 2):
+        lev, prev = M.levels[k], M.levels[k - 1]
+        eps_k = 1e-5 / 0.1 ** (k - 1)
+        allv = np.sort(np.concatenate(lev.patches))
+        assert np.array_equal(allv, np.arange(prev.n))
+        assert lev.n < 0.8 * prev.n
+        for mem in lev.patches:
+            if len(mem) < 2:
+                continue
+            E = energy.closed_energy(prev.A, mem) if k >= 2 else energy.interior_energy(prev.A, mem)
+            w, V = np.linalg.eigh(E)
+            eps = 1.0 / w[1]
+            Abar = prev.A[mem][:, mem].toarray()
+            delta = 1.0 / (V[:, 0] @ np.linalg.solve(Abar, V[:, 0]))
+            assert eps <= eps_k * (1 + 1e-12)
+            assert eps * delta <= 20.0 * (1 + 1e-12)
+        assert np.linalg.eigvalsh(lev.M.toarray()).min() >= 1 - 1e-10
+
+
+def test_eps_partition_coarse_spectrum_within_eps1():
+    """Theorem 2.6 / Lemma 3.3 on the prescribed-accuracy partition: with the
+    exact Psi = A^-1 Phi (Phi^T A^-1 Phi)^-1 the level-1 pencil (A^(1), M^(1))
+    reproduces mu_i = 1 / lambda_i(A) within eps_1 = 1e-5 (the interior patch
+    energies on level 1 make eps(P) a valid bound); the localized Psi needs
+    support radius 5 patch hops on this graph to keep that accuracy, while
+    radius 1 loses the low spectrum entirely (mu_1 error near 1)."""
+    p = wl.swissroll(1500, seed=2)
+    A = p.scipy()
+    mu0 = 1.0 / np.linalg.eigvalsh(A.toarray())[:12]
+    errs = {}
+    for name, kw in (("exact", dict(exact_max_n=10 ** 9)), ("r5", dict(r_hops=5)),
+                     ("r1", dict(r_hops=1))):
+        M = mm.build_mmd(A, coords=p.coords, levels=1, eps1=1e-5, eta=0.1, cbound=20.0, **kw)
+        lev = M.levels[1]
+        mu = 1.0 / sla.eigh(lev.A.toarray(), lev.M.toarray(), eigvals_only=True)[:12]
+        # Galerkin: mu^(1) <= mu (Courant-Fischer), up to the rounding of the
+        # formed Psi and A^(1), a modest multiple of u kappa(A) = 2.6e-10
+        assert np.all(mu <= mu0 * (1 + 2e-8))
+        errs[name] = np.max(np.abs(mu - mu0))
+        assert M.eps[1] <= 1e-5
+    assert errs["exact"] <= 1e-5
+    assert errs["r5"] <= 1e-5
+    assert errs["r1"] > 0.5
+
+
+def test_eps_partition_full_roll_level1_size():
+    """The paper's 20000-point SwissRoll with eps_1 = 1e-5, c = 20 has 5528
+    level-1 dofs (decomposition table of Section 7.2); this partition reading
+    gives a level-1 size within 2% of it."""
+    p = wl.swissroll(20000, seed=0)
+    P = mm.eps_partition(p.scipy(), p.coords, 1e-5, 20.0, False, 32)
+    assert abs(len(P) - 5528) <= 0.02 * 5528

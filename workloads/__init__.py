@@ -6,5 +6,5 @@ oracle and the GPU library may consume what it produces.
 """
 from .generators import (  # noqa: F401
     Problem, grid2d, grid3d_lognormal, rgg, rgg_batch, knn_gmm, random_csr,
-    random_block, by_name, rgg_window,
+    random_block, by_name, rgg_window, swissroll,
 )
