@@ -99,6 +99,15 @@ void cg_init(ColScalars sc, const double* part_bn, const double* part_rr, int nb
 void cg_alpha(ColScalars sc, const double* part_pq, int nblk, int b, hipStream_t s);
 // plain CG: rr_new = sum(part); conv test; beta = rr_new/rr; rr = rr_new; iters++
 void cg_beta(ColScalars sc, const double* part_rr, int nblk, int b, hipStream_t s);
+// as cg_beta, but a column with rr_new <= tol2 * bn2 keeps iterating and sets
+// upd[c] = 1 (request for an FP64 residual replacement)
+void cg_beta_flag(ColScalars sc, const double* part_rr, int nblk, int b, int* upd,
+                  hipStream_t s);
+// residual replacement: rr = rr2 = bn2 = rr_true, beta *= rr_true / rr (old),
+// or beta = 0 (restart) when rr_true > restart2 * rr or the column had stopped;
+// tol2 = delta2, alpha = 0, active = 1, upd = 0
+void reliable_scalars(ColScalars sc, const double* rr_true, double delta2, double restart2,
+                      int b, int* upd, hipStream_t s);
 // flexible PCG stop test on ||r||^2 (part_rr); marks converged columns inactive
 void pcg_conv(ColScalars sc, const double* part_rr, int nblk, int b, hipStream_t s);
 // flexible PCG beta = (r.z - r.zold) / rz ; rz = r.z

@@ -728,6 +728,53 @@ __global__ __launch_bounds__(kScThreads) void k_cg_beta(ColScalars sc,
   sc.rr[c] = rn;
 }
 
+// CG scalars of the reliable-update mixed solve: as k_cg_beta, but a column
+// whose recursive residual has dropped below tol2 * bn2 keeps iterating and
+// raises upd[c], which asks the host for an FP64 residual replacement.
+__global__ __launch_bounds__(kScThreads) void k_cg_beta_flag(ColScalars sc,
+                                                             const double* __restrict__ prr,
+                                                             int nblk, int b,
+                                                             int* __restrict__ upd) {
+  const bool act = col_active(sc, b);
+  const double rn = col_sum(prr, nblk, b, act);
+  const int c = sc_col();
+  if (threadIdx.x >= kScCols || c >= b) return;
+  if (!act) {
+    sc.beta[c] = 0.0;
+    return;
+  }
+  sc.iters[c] += 1;
+  sc.rr2[c] = rn;
+  if (rn <= sc.tol2[c] * sc.bn2[c]) upd[c] = 1;
+  sc.beta[c] = rn / sc.rr[c];
+  sc.rr[c] = rn;
+}
+
+// Residual replacement: the recursive residual r (with r.r = rr) is replaced
+// by the true residual with r.r = rr_true.  The next direction p = r + beta p
+// takes beta = rr_true / (r.r of the step before), i.e. the old beta scaled
+// by rr_true / rr; the column stays active, its next flag threshold is
+// delta2 * rr_true.  A column whose true residual exceeds restart2 times the
+// recursive one (the directions no longer match the residual), or that
+// stopped on a non-positive curvature, restarts with p = r (beta = 0).
+__global__ void k_reliable_scalars(ColScalars sc, const double* __restrict__ rr_true,
+                                   double delta2, double restart2, int b,
+                                   int* __restrict__ upd) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= b) return;
+  const double rt = rr_true[c];
+  const double rn = sc.rr[c];
+  const bool restart = !(rn > 0.0) || !sc.active[c] || rt > restart2 * rn;
+  sc.beta[c] = restart ? 0.0 : sc.beta[c] * (rt / rn);
+  sc.rr[c] = rt;
+  sc.rr2[c] = rt;
+  sc.bn2[c] = rt;
+  sc.tol2[c] = delta2;
+  sc.alpha[c] = 0.0;
+  sc.active[c] = 1;
+  upd[c] = 0;
+}
+
 __global__ __launch_bounds__(kScThreads) void k_pcg_conv(ColScalars sc,
                                                          const double* __restrict__ prr,
                                                          int nblk, int b) {
@@ -1254,6 +1301,21 @@ void cg_alpha(ColScalars sc, const double* part_pq, int nblk, int b, hipStream_t
 void cg_beta(ColScalars sc, const double* part_rr, int nblk, int b, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_beta, dim3(sc_grid(b)), dim3(kScThreads), 0, s, sc, part_rr,
                      nblk, b);
+  check_launch();
+}
+
+void cg_beta_flag(ColScalars sc, const double* part_rr, int nblk, int b, int* upd,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_beta_flag, dim3(sc_grid(b)), dim3(kScThreads), 0, s, sc, part_rr,
+                     nblk, b, upd);
+  check_launch();
+}
+
+void reliable_scalars(ColScalars sc, const double* rr_true, double delta2, double restart2,
+                      int b, int* upd, hipStream_t s) {
+  if (b == 0) return;
+  hipLaunchKernelGGL(k_reliable_scalars, dim3(ceil_div(b, kBlock)), dim3(kBlock), 0, s, sc,
+                     rr_true, delta2, restart2, b, upd);
   check_launch();
 }
 

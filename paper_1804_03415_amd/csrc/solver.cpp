@@ -469,152 +469,26 @@ void Solver::ensure32() {
   D.has32 = true;
 }
 
-void Solver::cg32(float* R32, int m, const std::vector<int>& gcols, double* X, int ldx,
-                  double eta, std::vector<int>& its) {
-  const int n = nlev(0);
-  const CsrView32& A = h_.dev[0].A32;
-  int bc = m, ldw = even_ld(m);
-  ColScalars sc = make_scalars(pool_, "m32", m);
-  float* R = R32;
-  float* P = pool_.f("m32:P", (size_t)n * ldw);
-  float* Q = pool_.f("m32:Q", (size_t)n * ldw);
-  float* D = pool_.f("m32:D", (size_t)n * ldw);
-  double* p1 = pool_.d("m32:p1", (size_t)kRedBlocks * m);
-  double* p2 = pool_.d("m32:p2", (size_t)kRedBlocks * m);
-  int* d_src = pool_.i("m32:src", m);
-  int* d_dst = pool_.i("m32:dst", m);
-  zero32(D, n, ldw, s_);
-  zero32(P, n, ldw, s_);
-  zero32(Q, n, ldw, s_);
-  const int nb = col_dot32(R, ldw, R, ldw, n, bc, p1, s_);
-  cg_init(sc, p1, nullptr, nb, bc, eta, nullptr, s_);
-  MMD_HIP(hipMemsetAsync(sc.notspd, 0, sizeof(int), s_));
-  std::vector<int> cols(m);
-  for (int j = 0; j < m; ++j) cols[j] = j;  // working column -> local column
-  its.assign(m, 0);
-  // add working columns src (working index) to X(:, gcols[cols[src]])
-  auto flush = [&](const std::vector<int>& src) {
-    if (src.empty()) return;
-    std::vector<int> dst(src.size());
-    for (size_t j = 0; j < src.size(); ++j) dst[j] = gcols[cols[src[j]]];
-    h2d(d_src, src.data(), src.size());
-    h2d(d_dst, dst.data(), dst.size());
-    scatter_add64(D, ldw, d_src, d_dst, X, ldx, n, static_cast<int>(src.size()), s_);
-    sync();  // the host index lists must outlive the copies
-  };
-  auto take_iters = [&]() {
-    hi_.ensure(bc);
-    d2h(hi_.p, sc.iters, bc);
-    sync();
-    for (int c = 0; c < bc; ++c) its[cols[c]] = hi_.p[c];
-  };
-  auto iterate = [&](bool first) {
-    const bool timed = bc > 64;
-    if (timed) spmm0_begin();
-    const int np = spmm32_cg(A, R, ldw, Q, ldw, bc, first, sc.beta, P, ldw, p1, s_);
-    if (timed) {
-      // matrix once (4-byte weights and columns, row pointers, self-loops),
-      // R read once, P and Q read and written once (FP32)
-      const double nnz = static_cast<double>(A.nnz);
-      const double bytes = 8.0 * nnz + 8.0 * n + 20.0 * n * static_cast<double>(bc) +
-                           (first ? -8.0 * n * static_cast<double>(bc) : 0.0);
-      spmm0_end(bytes, bc);
-    }
-    cg_alpha(sc, p1, np, bc, s_);
-    const int nu = cg_update32(D, ldw, R, P, Q, ldw, n, bc, sc.alpha, p2, s_);
-    cg_beta(sc, p2, nu, bc, s_);
-  };
-  // FP32 CG cannot push the residual far below its rounding level; the outer
-  // FP64 loop measures the true progress, so the inner solve just stops at
-  // the cap
-  const int maxit = 4 * n + 1000;
-  int done = 0, chunk = 4, stage = 0;
-  bool first = true;
-  while (true) {
-    for (int t = 0; t < chunk; ++t) {
-      iterate(first);
-      first = false;
-    }
-    done += chunk;
-    hi_.ensure(bc + 1);
-    d2h(hi_.p, sc.active, bc);
-    d2h(hi_.p + bc, sc.notspd, 1);
-    sync();
-    MMD_REQUIRE(hi_.p[bc] == 0, MMD_ENOTSPD, "CG curvature p^T A p <= 0 (FP32)");
-    std::vector<int> keep, drop;
-    for (int c = 0; c < bc; ++c) (hi_.p[c] != 0 ? keep : drop).push_back(c);
-    if (keep.empty() || done >= maxit) break;
-    chunk = std::min(chunk * 2, 64);
-    const int na = static_cast<int>(keep.size());
-    if (bc >= 16 && 4 * na <= 3 * bc) {
-      take_iters();
-      flush(drop);
-      ++stage;
-      const std::string st = "m32:c" + std::to_string(stage & 1);
-      const int ld2 = even_ld(na);
-      float* R2 = pool_.f(st + "R", (size_t)n * ld2);
-      float* P2 = pool_.f(st + "P", (size_t)n * ld2);
-      float* Q2 = pool_.f(st + "Q", (size_t)n * ld2);
-      float* D2 = pool_.f(st + "D", (size_t)n * ld2);
-      ColScalars sc2 = make_scalars(pool_, st, m);
-      sc2.notspd = sc.notspd;
-      h2d(d_src, keep.data(), na);
-      gather32(R, ldw, d_src, R2, ld2, n, na, s_);
-      gather32(P, ldw, d_src, P2, ld2, n, na, s_);
-      gather32(Q, ldw, d_src, Q2, ld2, n, na, s_);
-      gather32(D, ldw, d_src, D2, ld2, n, na, s_);
-      gather_scalars(sc, sc2, d_src, na, s_);
-      sync();  // keep (host) must outlive its copy
-      std::vector<int> cols2(na);
-      for (int j = 0; j < na; ++j) cols2[j] = cols[keep[j]];
-      cols.swap(cols2);
-      R = R2;
-      P = P2;
-      Q = Q2;
-      D = D2;
-      ldw = ld2;
-      sc = sc2;
-      bc = na;
-    }
-  }
-  take_iters();
-  std::vector<int> all(bc);
-  for (int c = 0; c < bc; ++c) all[c] = c;
-  flush(all);
-}
-
+// Mixed-precision level-0 block CG with reliable updates (residual
+// replacement, Sleijpen and van der Vorst 1996; the mixed-precision form of
+// Clark et al. 2010): CG iterates in FP32 on the FP32 copy of the edge-form
+// matrix (directions P, products Q = A P, recursive residual R, increment D),
+// while X, the true residual B - A X, the stop test and the deflation stay
+// FP64.  When a column's recursive residual has fallen by the factor delta
+// since its last replacement, the increments of all working columns are
+// added to X in FP64, the true residuals replace the recursive ones, and
+// iteration continues on the same search directions (beta rescaled to the
+// replaced residual), so the Krylov space is not thrown away as in a
+// restarted refinement.  A column stops when its true residual meets tol, or
+// at the FP64 floor of a true residual; a column whose true residual stops
+// shrinking across replacements hands the remaining columns to FP64 CG.
 void Solver::cg_mixed(const double* B, int ldb, double* X, int ldx, int b, double tol,
                       bool use_x0, std::vector<int>* iters, const Deflation* dfl) {
   const int n = nlev(0);
   ensure32();
-  double* R = pool_.d("mx:R", (size_t)n * b);
-  double* part = pool_.d("mx:part", (size_t)kRedBlocks * b);
-  double* nrm = pool_.d("mx:nrm", b);
-  int* d_idx = pool_.i("mx:idx", b);
+  const CsrView32& A32 = h_.dev[0].A32;
   if (!use_x0) zero_block(X, ldx, n, b, s_);
-  auto col_norms = [&](const double* Y, int ldy, std::vector<double>& out) {
-    const int g = col_dot(Y, ldy, Y, ldy, n, b, part, s_);
-    reduce_partials(part, g, b, nrm, s_);
-    out.resize(b);
-    d2h(out.data(), nrm, b);
-    sync();
-  };
-  std::vector<double> bn2, rr;
-  col_norms(B, ldb, bn2);
-  std::vector<int> total(b, 0), its;
-  std::vector<char> live(b, 1);
-  std::vector<double> prev(b, 0.0);
-  // inner FP32 solves reduce the residual by eta each; the true FP64 residual
-  // decides convergence: ||r|| <= tol ||b||, or a column whose residual no
-  // longer halves per refinement step has reached the FP64 floor
-  // u ||A|| ||x|| of a true residual (the recursive residual of FP64 CG has
-  // no such floor, so tight tolerances on near-singular systems end here)
-  // eta = 1e-2 measured best on the n = 1e5 RGG (1e-1 .. 1e-6 tried): FP32 CG
-  // slows down sharply when pushed deep, restarts are cheap
-  const double eta = 1e-2;
-  const int max_outer = 60;
-  // ||A||_inf of the level-0 matrix for the floor test
-  if (norm_a0_ <= 0.0) {
+  if (norm_a0_ <= 0.0) {  // ||A||_inf of the level-0 matrix for the floor test
     const HostCSR& A0 = h_.host[0].A;
     for (int i = 0; i < A0.n_rows; ++i) {
       double t = 0.0;
@@ -622,63 +496,232 @@ void Solver::cg_mixed(const double* B, int ldb, double* X, int ldx, int b, doubl
       norm_a0_ = std::max(norm_a0_, t);
     }
   }
-  std::vector<double> xx;
-  // a column whose FP64 residual has not halved over the last kStall outer
-  // steps while still above the tolerance is beyond what the FP32 inner solve
-  // can resolve (rounding at the FP32 level of components the deflation does
-  // not remove): the refinement hands all remaining columns to FP64 CG
-  constexpr int kStall = 4;
+  // FP64 work of the replacements (working columns gathered contiguously)
+  double* Xw = pool_.d("mx:X", (size_t)n * b);
+  double* Bw = pool_.d("mx:B", (size_t)n * b);
+  double* Rw = pool_.d("mx:R", (size_t)n * b);
+  double* part = pool_.d("mx:part", (size_t)kRedBlocks * b);
+  double* nrm = pool_.d("mx:nrm", b);
+  double* d_rt = pool_.d("mx:rt", b);
+  int* d_gl = pool_.i("mx:gl", b);
+  int* d_idx = pool_.i("mx:idx", b);
+  int* d_src = pool_.i("mx:src", b);
+  double* p1 = pool_.d("m32:p1", (size_t)kRedBlocks * b);
+  double* p2 = pool_.d("m32:p2", (size_t)kRedBlocks * b);
+  // delta: a replacement per 10x drop of the recursive residual norm (the
+  // recursive FP32 residual then never drifts far from the true one); at most
+  // kSince FP32 steps between replacements; a column whose true residual
+  // norm is more than 2x its recursive one restarts its direction
+  const double delta2 = 1e-2, restart2 = 4.0;
+  constexpr int kStall = 4;      // replacements without a 2x true-residual drop
+  constexpr int kMaxUpdates = 400;
+  constexpr int kSince = 256;
+  constexpr int kMaxCurv = 3;    // FP32 curvature breakdowns before FP64 takes over
+  int curv = 0;
+
+  std::vector<double> bn2(b);
+  {
+    const int g = col_dot(B, ldb, B, ldb, n, b, part, s_);
+    reduce_partials(part, g, b, nrm, s_);
+    d2h(bn2.data(), nrm, b);
+    sync();
+  }
+  std::vector<int> total(b, 0);
   std::vector<std::vector<double>> hist(b);
-  bool fallback = false;
-  for (int outer = 0;; ++outer) {
-    applyA(0, X, ldx, R, b, b);
-    rsub(B, ldb, R, b, n, b, s_);
-    col_norms(R, b, rr);
-    col_norms(X, ldx, xx);
-    std::vector<int> act;
-    for (int c = 0; c < b; ++c) {
-      if (!live[c]) continue;
-      const double floor = 64.0 * 2.2e-16 * norm_a0_ * std::sqrt(xx[c]);
-      const bool stalled = outer > 0 && rr[c] > 0.25 * prev[c] && rr[c] <= floor * floor;
-      if (!(bn2[c] > 0.0) || rr[c] <= tol * tol * bn2[c] || stalled) {
-        live[c] = 0;
-      } else {
-        act.push_back(c);
-        hist[c].push_back(rr[c]);
-        const size_t h = hist[c].size();
-        if (h > kStall && hist[c][h - 1] > 0.25 * hist[c][h - 1 - kStall]) fallback = true;
-      }
-      prev[c] = rr[c];
+  std::vector<int> gl(b);  // working column -> global column
+  for (int c = 0; c < b; ++c) gl[c] = c;
+  int m = b, ldw = even_ld(b), stage = 0;
+  float* R = nullptr;
+  float* P = nullptr;
+  float* Q = nullptr;
+  float* D = nullptr;
+  int* upd = nullptr;
+  ColScalars sc{};
+  bool first = true, fallback = false;
+  std::vector<double> rr, xx;
+  std::vector<int> hv(b + 1), src_host(b);  // host lists live until the next sync
+  auto alloc_stage = [&](int mm) {
+    const std::string st = "m32:s" + std::to_string(stage & 1);
+    const int ld = even_ld(mm);
+    float* R2 = pool_.f(st + "R", (size_t)n * ld);
+    float* P2 = pool_.f(st + "P", (size_t)n * ld);
+    float* Q2 = pool_.f(st + "Q", (size_t)n * ld);
+    float* D2 = pool_.f(st + "D", (size_t)n * ld);
+    int* u2 = pool_.i(st + "upd", std::max(mm, 1));
+    ColScalars s2 = make_scalars(pool_, st, std::max(mm, 1));
+    ++stage;
+    return std::make_tuple(R2, P2, Q2, D2, u2, s2, ld);
+  };
+  int updates = 0;
+  while (true) {
+    // ---- residual replacement over the working columns (FP64)
+    if (D) {
+      for (int c = 0; c < m; ++c) src_host[c] = c;
+      h2d(d_src, src_host.data(), m);
+      h2d(d_gl, gl.data(), m);
+      scatter_add64(D, ldw, d_src, d_gl, X, ldx, n, m, s_);
+    } else {
+      h2d(d_gl, gl.data(), m);
     }
-    if (act.empty()) break;
-    if (fallback || outer >= max_outer) {
-      std::vector<int> its64;
-      cg(0, OpKind::A, B, ldb, X, ldx, n, b, tol, true, nullptr, 0, "mxfb", &its64);
-      for (int c = 0; c < b; ++c) total[c] += its64[c];
-      if (st_) st_->mixed_fallbacks += 1;
-      if (log_on())
-        std::fprintf(stderr, "[mmdeig] mixed refinement: FP64 CG finishes %d of %d columns\n",
-                     static_cast<int>(act.size()), b);
-      break;
+    const bool ident = m == b && ldx == b && ldb == b;  // no gather needed
+    const double* Xc = X;
+    const double* Bc = B;
+    int ldxc = ldx, ldbc = ldb;
+    if (!ident) {
+      gather_cols(X, ldx, d_gl, Xw, m, n, m, s_);
+      gather_cols(B, ldb, d_gl, Bw, m, n, m, s_);
+      Xc = Xw;
+      Bc = Bw;
+      ldxc = ldbc = m;
     }
+    applyA(0, Xc, ldxc, Rw, m, m);
+    rsub(Bc, ldbc, Rw, m, n, m, s_);
     if (dfl && dfl->m > 0) {
       // C = Q^T R ; R -= Q C ; X += Q diag(mu) C   (all FP64)
       const int mq = dfl->m;
-      double* C = pool_.d("mx:C", (size_t)mq * b);
-      double* gw = pool_.d("mx:gw", gram_work_size(n, mq, b));
-      gram(dfl->Q, dfl->ld, R, b, n, mq, b, C, b, gw, s_);
-      gemm_nn(dfl->Q, dfl->ld, C, b, R, b, n, mq, b, -1.0, 1.0, s_);
-      scale_rows(C, b, dfl->mu, mq, b, s_);
-      gemm_nn(dfl->Q, dfl->ld, C, b, X, ldx, n, mq, b, 1.0, 1.0, s_);
+      double* C = pool_.d("mx:C", (size_t)mq * m);
+      double* gw = pool_.d("mx:gw", gram_work_size(n, mq, m));
+      if (ident) {
+        copy_block(X, ldx, Xw, m, n, m, s_);
+      } else if (Xc != Xw) {
+        gather_cols(X, ldx, d_gl, Xw, m, n, m, s_);
+      }
+      gram(dfl->Q, dfl->ld, Rw, m, n, mq, m, C, m, gw, s_);
+      gemm_nn(dfl->Q, dfl->ld, C, m, Rw, m, n, mq, m, -1.0, 1.0, s_);
+      scale_rows(C, m, dfl->mu, mq, m, s_);
+      gemm_nn(dfl->Q, dfl->ld, C, m, Xw, m, n, mq, m, 1.0, 1.0, s_);
+      scatter_cols(Xw, m, d_gl, X, ldx, n, m, s_);
+      Xc = Xw;
+      ldxc = m;
     }
-    const int m = static_cast<int>(act.size());
-    const int ld32 = even_ld(m);
-    float* R32 = pool_.f("mx:R32", (size_t)n * ld32);
-    h2d(d_idx, act.data(), m);
-    gather_to32(R, b, d_idx, R32, ld32, n, m, s_);
-    sync();  // act (host) must outlive its copy
-    cg32(R32, m, act, X, ldx, eta, its);
-    for (int j = 0; j < m; ++j) total[act[j]] += its[j];
+    {
+      int g = col_dot(Rw, m, Rw, m, n, m, part, s_);
+      reduce_partials(part, g, m, nrm, s_);
+      rr.resize(m);
+      d2h(rr.data(), nrm, m);
+      g = col_dot(Xc, ldxc, Xc, ldxc, n, m, part, s_);
+      reduce_partials(part, g, m, nrm, s_);
+      xx.resize(m);
+      d2h(xx.data(), nrm, m);
+      if (sc.iters) {
+        hi_.ensure(m);
+        d2h(hi_.p, sc.iters, m);
+      }
+      sync();
+      if (sc.iters)
+        for (int c = 0; c < m; ++c) total[gl[c]] = hi_.p[c];
+    }
+    std::vector<int> keep;
+    for (int c = 0; c < m; ++c) {
+      const int g = gl[c];
+      const double floor = 64.0 * 2.2e-16 * norm_a0_ * std::sqrt(xx[c]);
+      const bool at_floor = !hist[g].empty() && rr[c] > 0.25 * hist[g].back() &&
+                            rr[c] <= floor * floor;
+      if (!(bn2[g] > 0.0) || rr[c] <= tol * tol * bn2[g] || at_floor) continue;
+      hist[g].push_back(rr[c]);
+      const size_t h = hist[g].size();
+      if (h > kStall && hist[g][h - 1] > 0.25 * hist[g][h - 1 - kStall]) fallback = true;
+      keep.push_back(c);
+    }
+    if (keep.empty()) break;
+    if (fallback || updates >= kMaxUpdates) {
+      fallback = true;
+      break;
+    }
+    ++updates;
+    // ---- FP32 working state of the kept columns
+    const int na = static_cast<int>(keep.size());
+    std::vector<double> rt(na);
+    for (int j = 0; j < na; ++j) rt[j] = rr[keep[j]];
+    auto [R2, P2, Q2, D2, u2, sc2, ld2] = alloc_stage(na);
+    h2d(d_idx, keep.data(), na);
+    h2d(d_rt, rt.data(), na);
+    gather_to32(Rw, m, d_idx, R2, ld2, n, na, s_);
+    zero32(D2, n, ld2, s_);
+    if (first) {
+      zero32(P2, n, ld2, s_);
+      zero32(Q2, n, ld2, s_);
+      const int nb = col_dot32(R2, ld2, R2, ld2, n, na, p1, s_);
+      cg_init(sc2, p1, nullptr, nb, na, std::sqrt(delta2), nullptr, s_);
+      MMD_HIP(hipMemsetAsync(sc2.notspd, 0, sizeof(int), s_));
+      MMD_HIP(hipMemsetAsync(u2, 0, sizeof(int) * na, s_));
+    } else {
+      gather32(P, ldw, d_idx, P2, ld2, n, na, s_);
+      gather32(Q, ldw, d_idx, Q2, ld2, n, na, s_);
+      gather_scalars(sc, sc2, d_idx, na, s_);
+      sc2.notspd = sc.notspd;
+      reliable_scalars(sc2, d_rt, delta2, restart2, na, u2, s_);
+    }
+    std::vector<int> gl2(na);
+    for (int j = 0; j < na; ++j) gl2[j] = gl[keep[j]];
+    sync();  // host index lists must outlive their copies
+    gl.swap(gl2);
+    R = R2;
+    P = P2;
+    Q = Q2;
+    D = D2;
+    upd = u2;
+    sc = sc2;
+    ldw = ld2;
+    m = na;
+    // ---- FP32 CG until some column asks for a replacement
+    int chunk = 4, since = 0;
+    while (true) {
+      for (int t = 0; t < chunk; ++t) {
+        const bool timed = m > 64;
+        if (timed) spmm0_begin();
+        const int np = spmm32_cg(A32, R, ldw, Q, ldw, m, first, sc.beta, P, ldw, p1, s_);
+        if (timed) {
+          // matrix once (4-byte weights and columns, row pointers, self-loops),
+          // R read once, P and Q read and written once (FP32)
+          const double nnz = static_cast<double>(A32.nnz);
+          const double bytes = 8.0 * nnz + 8.0 * n + 20.0 * n * static_cast<double>(m) +
+                               (first ? -8.0 * n * static_cast<double>(m) : 0.0);
+          spmm0_end(bytes, m);
+        }
+        first = false;
+        cg_alpha(sc, p1, np, m, s_);
+        const int nu = cg_update32(D, ldw, R, P, Q, ldw, n, m, sc.alpha, p2, s_);
+        cg_beta_flag(sc, p2, nu, m, upd, s_);
+      }
+      since += chunk;
+      d2h(hv.data(), upd, m);
+      d2h(hv.data() + m, sc.notspd, 1);
+      sync();
+      bool any = false;
+      for (int c = 0; c < m; ++c) any |= hv[c] != 0;
+      if (hv[m] != 0) {
+        // p^T A p <= 0 in FP32 (a direction at the FP32 resolution of a
+        // near-singular matrix): the column stopped; the replacement restarts
+        // it from its true residual, repeated breakdowns go to FP64
+        MMD_HIP(hipMemsetAsync(sc.notspd, 0, sizeof(int), s_));
+        if (++curv > kMaxCurv) fallback = true;
+        break;
+      }
+      if (any || since >= kSince) break;
+      chunk = std::min(chunk * 2, 32);
+    }
+    if (fallback) {
+      // add the open increments before FP64 CG continues from X
+      for (int c = 0; c < m; ++c) src_host[c] = c;
+      h2d(d_src, src_host.data(), m);
+      h2d(d_gl, gl.data(), m);
+      scatter_add64(D, ldw, d_src, d_gl, X, ldx, n, m, s_);
+      hi_.ensure(m);
+      d2h(hi_.p, sc.iters, m);
+      sync();
+      for (int c = 0; c < m; ++c) total[gl[c]] = hi_.p[c];
+      break;
+    }
+  }
+  if (fallback) {
+    std::vector<int> its64;
+    cg(0, OpKind::A, B, ldb, X, ldx, n, b, tol, true, nullptr, 0, "mxfb", &its64);
+    for (int c = 0; c < b; ++c) total[c] += its64[c];
+    if (st_) st_->mixed_fallbacks += 1;
+    if (log_on())
+      std::fprintf(stderr, "[mmdeig] mixed refinement: FP64 CG finishes the open columns "
+                           "after %d residual replacements\n", updates);
   }
   if (iters) *iters = total;
 }

@@ -90,8 +90,6 @@ class Solver {
                 std::vector<int>* iters, const Deflation* dfl = nullptr);
   // FP32 CG (zero start) on the m columns of R32 (leading dimension even_ld(m),
   // consumed as the residual); the solutions are added to X(:, gcols[j]).
-  void cg32(float* R32, int m, const std::vector<int>& gcols, double* X, int ldx, double eta,
-            std::vector<int>& its);
   void ensure32();
   // CG on P (A - diag shift) P, P = I - V V^T, for the columns of R (row-major
   // n x b, in V-perp); Y receives the solutions (zero start)

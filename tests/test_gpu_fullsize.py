@@ -58,6 +58,24 @@ def per_pair(A, lam, Vh, lam_ref, Vh_ref):
     return rho, e, angle, full
 
 
+def angle_bound(A, lam, Vh, lam_ref, Vh_ref):
+    """Davis-Kahan sin-theta bound per pair for two approximations of the same
+    eigenvector cluster: sin angle <= (||r|| + ||r_ref||) / gap, with r the
+    cluster's residual block and gap the distance of the cluster's
+    eigenvalues to the rest of the computed spectrum (both runs' residuals
+    are at most about 1e-9 lambda, so close clusters allow angles above 1e-8)."""
+    cl = dense.clusters(lam_ref)
+    out = np.zeros(lam.size)
+    for c in cl:
+        lo_gap = lam_ref[c[0]] - lam_ref[c[0] - 1] if c[0] > 0 else np.inf
+        hi_gap = lam_ref[c[-1] + 1] - lam_ref[c[-1]] if c[-1] + 1 < lam.size else np.inf
+        gap = min(lo_gap, hi_gap)
+        R = A @ Vh[:, c] - Vh[:, c] * lam[c][None, :]
+        Rr = A @ Vh_ref[:, c] - Vh_ref[:, c] * lam_ref[c][None, :]
+        out[c] = (np.linalg.norm(R, 2) + np.linalg.norm(Rr, 2)) / gap
+    return out
+
+
 @pytest.fixture(scope="module")
 def torch_cuda():
     import torch
@@ -102,7 +120,9 @@ def test_diffusion_64cubed_500_fp64_and_mixed(torch_cuda):
     """3-D 7-point lognormal diffusion, n = 262144, 500 pairs, FP64 and the
     mixed form (FP32 CG inside FP64 refinement): every pair of both runs meets
     the residual target, and per eigenpair the mixed run's relative eigenvalue
-    difference (1e-10) and cluster angle (1e-8) against the FP64 run."""
+    difference (1e-10) and cluster angle against the FP64 run: 1e-8, or the
+    Davis-Kahan bound of the two runs' residuals where a neighbouring
+    eigenvalue is close."""
     from paper_1804_03415_amd import Decomposition
     p = wl.grid3d_lognormal(64, 0)
     A = p.scipy()
@@ -117,7 +137,10 @@ def test_diffusion_64cubed_500_fp64_and_mixed(torch_cuda):
     rho, e, angle, full = per_pair(A, lm, Vmh, lam, Vh)
     assert rho.max() <= 1e-8
     assert e.max() <= 1e-10
-    assert angle[full].max() <= 1e-8
+    # 1e-8 where the clusters are well separated, else the sin-theta bound
+    bar = np.maximum(1e-8, angle_bound(A, lm, Vmh, lam, Vh))
+    assert np.all(angle[full] <= bar[full])
+    assert np.median(angle[full]) <= 1e-9
 
 
 @pytest.mark.timeout(900)
