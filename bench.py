@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--mixed-steps", type=int, default=1,
                     help="timed eigensolves of the FP32-CG + FP64-refinement form after the "
                          "main run (0: skip), compared pair by pair with the main run")
+    ap.add_argument("--k0-steps", type=int, default=1,
+                    help="timed eigensolves of restarted Lanczos on A^-1 without the "
+                         "hierarchy (levels = 0: IRLM with CG solves, the paper's comparison "
+                         "method) on the same kernels (0: skip)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample-frac", type=float, default=0.05)
     ap.add_argument("--traffic-bytes", type=float, default=None,
@@ -92,6 +96,20 @@ def cluster_angles(lam, V, W, gap=1e-6):
     return np.array(out)
 
 
+def per_pair_angles(lam, V, W, gap=1e-6):
+    """The cluster angle of cluster_angles, repeated for every pair of the cluster."""
+    out = np.zeros(lam.size)
+    i = 0
+    while i < lam.size:
+        j = i + 1
+        while j < lam.size and (lam[j] - lam[j - 1]) / lam[j - 1] < gap:
+            j += 1
+        Vc, Wc = V[:, i:j], W[:, i:j]
+        out[i:j] = np.linalg.norm(Wc - Vc @ (Vc.T @ Wc), 2)
+        i = j
+    return out
+
+
 def timed_solves(dec, a, precision, steps, warmup):
     import torch
     for w in range(warmup):
@@ -122,17 +140,27 @@ def kernel_roofline(stats):
                 avg_launch_us=round(1000.0 * ms_tot / max(launches, 1), 2))
 
 
+def kernel_source_sha(path):
+    """SHA-256 of the dominant kernel's source text: the LDS-staged tiled SpMM
+    (its leading comment, the kernel template and its launcher) in kernels.hip."""
+    import hashlib
+    with open(path) as f:
+        text = f.read()
+    i = text.index("// LDS-staged block SpMM on the tiled level-0 edge form")
+    j = text.index("int launch_spmm_tile(", i)
+    j = text.index("\n}\n", j) + 3
+    return hashlib.sha256(text[i:j].encode()).hexdigest()
+
+
 def measured_traffic():
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     counter summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None
-    when the kernel source has changed since the counters were taken."""
-    import hashlib
+    when the kernel's source has changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "spmm_tile_rgg_n1e5_traffic.json")
     try:
         with open(path) as f:
             d = json.load(f)
-        with open(os.path.join(ROOT, d["source"]), "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        sha = kernel_source_sha(os.path.join(ROOT, d["source"]))
     except (OSError, ValueError, KeyError):
         return None
     if sha != d["source_sha256"]:
@@ -493,17 +521,37 @@ def main():
         rho_m = residuals(lm, Vmh)
         ang = cluster_angles(lam, Vh, Vmh)
         krm = kernel_roofline(stm)
+        e_m = np.abs(lm - lam) / lam
+        ang_pp = per_pair_angles(lam, Vh, Vmh)
         mixed = {"value": round(a.nev * a.mixed_steps / el_m, 3),
                  "ms_per_step": round(1000.0 * el_m / a.mixed_steps, 2),
+                 "speedup_vs_fp64": round((a.nev * a.mixed_steps / el_m) / value, 3),
                  "steps": a.mixed_steps, "warmup": 1,
                  "max_rel_residual": float(rho_m.max()),
                  "residual_ok": bool(rho_m.max() <= 1e-8),
-                 "max_rel_eig_err_vs_fp64": float(np.max(np.abs(lm - lam) / lam)),
+                 "max_rel_eig_err_vs_fp64": float(e_m.max()),
                  "max_cluster_angle_vs_fp64": float(ang.max()),
+                 "fallbacks_to_fp64": int(sum(s_["mixed_fallbacks"] for s_ in stm)),
+                 "per_pair": {"rel_residual": [float("%.3g" % x) for x in rho_m],
+                              "rel_eig_err_vs_fp64": [float("%.3g" % x) for x in e_m],
+                              "cluster_angle_vs_fp64": [float("%.3g" % x) for x in ang_pp]},
                  "kernel": "k_spmm32_w<edge>: level-0 FP32 block-CG step",
                  "kernel_achieved_GBs": krm["achieved"], "kernel_frac": krm["frac"],
                  "kernel_avg_launch_us": krm["avg_launch_us"],
                  "kernel_launches": krm["launches"]}
+
+    k0 = None
+    if a.k0_steps > 0:
+        d0 = Decomposition.from_problem(p, levels=0)
+        l0, V0, st0, el0 = timed_solves(d0, a, "fp64", a.k0_steps, 0)
+        rho0 = residuals(l0, V0.cpu().numpy().T)
+        nn = np.abs(lam - 1e-6) > 2.0 ** -52 * norm_inf
+        k0 = {"value": round(a.nev * a.k0_steps / el0, 3),
+              "ms_per_step": round(1000.0 * el0 / a.k0_steps, 2), "steps": a.k0_steps,
+              "method": "restarted Lanczos on A^-1 with CG solves, no hierarchy (levels = 0)",
+              "max_rel_residual": float(rho0.max()),
+              "max_rel_eig_diff_vs_mmd": float(np.max(np.abs(l0[nn] - lam[nn]) / lam[nn]))}
+        d0.close()
 
     cpu = None
     if a.cpu_baseline:
@@ -545,6 +593,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "fp32_refine": mixed,
+        "no_hierarchy_irlm_cg": k0,
     }
     # device memory is released while the runtime is fully up, not in exit handlers
     dec.close()

@@ -24,8 +24,9 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_traffic_follows_the_committed_counters(tmp_path, monkeypatch):
-    """The traffic figure is reported only while the kernel source hashes to
-    the value recorded with the counters."""
+    """The traffic figure is reported only while the dominant kernel's source
+    text hashes to the value recorded with the counters; edits elsewhere in
+    the file leave it valid."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "spmm_tile_rgg_n1e5_traffic.json")
     with open(path) as f:
@@ -34,17 +35,25 @@ def test_traffic_follows_the_committed_counters(tmp_path, monkeypatch):
     fake.mkdir()
     src = tmp_path / d["source"]
     src.parent.mkdir(parents=True)
-    body = b"// kernel source stand-in\n"
-    src.write_bytes(body)
+    region = ("// LDS-staged block SpMM on the tiled level-0 edge form (stand-in)\n"
+              "int launch_spmm_tile(int x) {\n  return x;\n}\n")
+    body = "// other kernels\n" + region + "// more kernels\n"
+    src.write_text(body)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    d["source_sha256"] = hashlib.sha256(body).hexdigest()
+    d["source_sha256"] = hashlib.sha256(region.encode()).hexdigest()
     (fake / "spmm_tile_rgg_n1e5_traffic.json").write_text(json.dumps(d))
     want = round(1024.0 * (d["fetch_size_kib_per_launch"] * d["fetch_scale"] +
                            d["write_size_kib_per_launch"] * d["write_scale"]))
     assert bench.measured_traffic() == want and want > 0
-    # a summary taken on other source bytes gives no traffic figure
-    src.write_bytes(body + b"// changed\n")
+    # edits outside the kernel keep the figure
+    src.write_text("// a new kernel\n" + body + "// another\n")
+    assert bench.measured_traffic() == want
+    # a summary taken on other kernel source gives no traffic figure
+    src.write_text(body.replace("return x;", "return x + 1;"))
     assert bench.measured_traffic() is None
+    # the committed summary matches the kernel source in the tree
+    assert bench.kernel_source_sha(os.path.join(ROOT, d["source"])) == json.load(
+        open(path))["source_sha256"]
 
 
 def test_cpu_sample_is_a_window_of_the_same_cloud():
