@@ -41,7 +41,7 @@ struct LevelHost {
 struct LevelDev {
   DBuf<int> a_ptr, a_col, m_ptr, m_col, p_ptr, p_col, h_ptr, h_mem;
   DBuf<double> a_val, a_diag, m_val, p_val, h_u, h_scale;
-  DBuf<int> t_uptr, t_urow;  // level-0 row-block tiling (kernels.h)
+  DBuf<int> t_row, t_uptr, t_urow;  // level-0 row-block tiling (kernels.h)
   DBuf<unsigned short> t_lcol;
   CsrView A, M, Psi;
   HouseView H;  // transfer (k-1 -> k): U^(k)

@@ -21,20 +21,21 @@ struct CsrView {
   const double* diag = nullptr;  // non-null: edge form y = s x + sum w (x_i - x_j)
   double avg_row = 1.0;
   // Row-block tiling of the edge form (level 0; t_uptr == nullptr: none).
-  // Block t owns rows [t * kTileRows, min(n, (t + 1) * kTileRows)); its
+  // Block t owns rows [t_row[t], t_row[t + 1]) (at most kTileRows); its
   // column set U_t lists those rows first, in order, then the other columns
   // its rows touch, ascending: t_urow[t_uptr[t] .. t_uptr[t + 1]).  t_lcol[q]
   // is the position in U_t of col[q].  Every |U_t| <= kTileCols and every
   // block holds at most kTileNnz entries.
+  const int* t_row = nullptr;
   const int* t_uptr = nullptr;
   const int* t_urow = nullptr;
   const unsigned short* t_lcol = nullptr;
   int t_nblk = 0;
 };
 
-constexpr int kTileRows = 32;   // rows per tile block
-constexpr int kTileCols = 128;  // max distinct columns (gathered rows) per block
-constexpr int kTileNnz = 1024;  // max entries per block
+constexpr int kTileRows = 32;   // max rows per tile block
+constexpr int kTileCols = 64;   // max distinct columns (gathered rows) per block
+constexpr int kTileNnz = 768;   // max entries per block
 
 // Patch Householder data of one level transfer (k-1 -> k).
 struct HouseView {

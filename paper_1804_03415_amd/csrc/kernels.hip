@@ -276,30 +276,36 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
 }
 
 // LDS-staged block SpMM on the tiled level-0 edge form (CsrView::t_uptr):
-// a workgroup takes a tile of kTileRows consecutive rows and one 64-column
-// slice, copies the X rows its entries touch (own rows first, then the
-// halo) into LDS with one coalesced 512-byte load per row, together with
-// the tile's weights, local column positions and row pointers, and then
-// forms every row from LDS.  Each gathered row of X leaves L2 once per tile
+// a workgroup takes a tile of up to kTileRows consecutive rows whose entries
+// touch at most kTileCols rows, and one 64-column slice, copies the X rows
+// its entries touch (own rows first, then the halo) into LDS with one
+// coalesced 512-byte load per row, together with the tile's weights, local
+// column positions and row pointers, and then forms every row from LDS.
+// 40 KB of LDS and at most 128 VGPRs per workgroup: four workgroups (16
+// wavefronts) per CU.  Caps measured on the n = 1e5 RGG: 128 staged rows
+// (two workgroups per CU) 337 us per launch, 80 rows (three) 296 us, 64 rows
+// (four) 282 us, 48 rows with 16-row tiles (five) 285 us.  Each gathered row of X leaves L2 once per tile
 // instead of once per entry (about 2.3 reads per row against 11 for the
 // RGG in Morton order).  Tiles are dealt to the 8 XCDs in contiguous ranges,
 // so neighbouring tiles that share halo rows run on the same L2.  Fused CG
 // epilogue as in k_spmm_r64.
 template <bool FUSE>
-__global__ __launch_bounds__(kBlock) void k_spmm_tile(
+__global__ __launch_bounds__(kBlock, 4) void k_spmm_tile(
     int n_rows, const int* __restrict__ rowptr, const double* __restrict__ val,
-    const double* __restrict__ diag, const int* __restrict__ uptr,
-    const int* __restrict__ urow, const unsigned short* __restrict__ lcol, int nblk,
+    const double* __restrict__ diag, const int* __restrict__ trow,
+    const int* __restrict__ uptr, const int* __restrict__ urow,
+    const unsigned short* __restrict__ lcol, int nblk,
     const double* __restrict__ X, int ldx, double* __restrict__ Y, int ldy, int b, int first,
     const double* __restrict__ beta, double* __restrict__ P, int ldp,
     double* __restrict__ partial) {
   constexpr int WPB = kBlock / kWave;
   constexpr int RPW = kTileRows / WPB;  // rows per wavefront and tile
-  __shared__ double sx[kTileCols * kWave];
+  __shared__ double sx[kTileCols * kWave];  // also the partial-sum buffer at the end
   __shared__ double sv[kTileNnz];
   __shared__ unsigned short sc[kTileNnz];
   __shared__ int sp[kTileRows + 1];
-  __shared__ double red[WPB * kWave];
+  double* red = sx;
+  static_assert(kTileCols >= WPB, "the reduction reuses the staging buffer");
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
   const int cc = blockIdx.y * kWave + lane;
@@ -313,8 +319,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm_tile(
   const int tpx = (nblk + nx - 1) / nx;
   const int thi = min(nblk, (xcd + 1) * tpx);
   for (int t = xcd * tpx + bl; t < thi; t += bpx) {
-    const int r0 = t * kTileRows;
-    const int r1 = min(n_rows, r0 + kTileRows);
+    const int r0 = trow[t];
+    const int r1 = trow[t + 1];
     const int u0 = uptr[t], nu = uptr[t + 1] - u0;
     const int e0 = rowptr[r0], ne = rowptr[r1] - e0;
     // own-row streams of this wavefront's rows first: they do not wait for
@@ -328,32 +334,46 @@ __global__ __launch_bounds__(kBlock) void k_spmm_tile(
       yo[k] = ok ? __builtin_nontemporal_load(Y + ri * ldy + cx) : 0.0;
       po[k] = ok ? __builtin_nontemporal_load(P + ri * ldp + cx) : 0.0;
     }
-    // staging of the tile's X rows: lane j of wavefront w holds the row of
-    // slot w + 4 j, broadcast with readlane, so a wavefront's row loads issue
-    // in groups of 8 instead of one index-then-row round trip per slot
+    // staging of the tile: every global load of the tile is issued before
+    // the first LDS store, so the tile waits for one memory round trip.
+    // The entries (weights, local positions) come first, then the X rows:
+    // lane j of wavefront w holds the row of slot w + 4 j, broadcast with
+    // readlane, and all of the wavefront's slots are loaded in one batch.
     {
+      constexpr int EPT = kTileNnz / kBlock;  // entries per thread
+      double ev[EPT];
+      unsigned short ec[EPT];
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const int e = threadIdx.x + q * kBlock;
+        ev[q] = e < ne ? val[e0 + e] : 0.0;
+        ec[q] = e < ne ? lcol[e0 + e] : 0;
+      }
+      const int rp = threadIdx.x <= r1 - r0 ? rowptr[r0 + threadIdx.x] - e0 : 0;
       constexpr int SPW = kTileCols / WPB;  // slots per wavefront
       const int myu = wid + WPB * lane;
       const int ridx = (lane < SPW && myu < nu) ? urow[u0 + myu] : -1;
-      for (int g = 0; g < SPW && wid + WPB * g < nu; g += 8) {
-        double v[8];
+      double v[SPW];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int j = __builtin_amdgcn_readlane(ridx, g + q);
-          v[q] = j >= 0 ? X[(size_t)j * ldx + cx] : 0.0;
-        }
+      for (int q = 0; q < SPW; ++q) {
+        const int j = __builtin_amdgcn_readlane(ridx, q);
+        v[q] = j >= 0 ? X[(size_t)j * ldx + cx] : 0.0;
+      }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int u = wid + WPB * (g + q);
-          if (u < nu) sx[u * kWave + lane] = v[q];
+      for (int q = 0; q < EPT; ++q) {
+        const int e = threadIdx.x + q * kBlock;
+        if (e < ne) {
+          sv[e] = ev[q];
+          sc[e] = ec[q];
         }
       }
+      if (threadIdx.x <= r1 - r0) sp[threadIdx.x] = rp;
+#pragma unroll
+      for (int q = 0; q < SPW; ++q) {
+        const int u = wid + WPB * q;
+        if (u < nu) sx[u * kWave + lane] = v[q];
+      }
     }
-    for (int q = threadIdx.x; q < ne; q += kBlock) {
-      sv[q] = val[e0 + q];
-      sc[q] = lcol[e0 + q];
-    }
-    for (int q = threadIdx.x; q <= r1 - r0; q += kBlock) sp[q] = rowptr[r0 + q] - e0;
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < RPW; ++k) {
@@ -421,11 +441,11 @@ int launch_spmm_tile(const CsrView& A, const double* X, int ldx, double* Y, int 
   dim3 grid(gx, ceil_div(b, kWave));
   if (fuse)
     hipLaunchKernelGGL(k_spmm_tile<true>, grid, dim3(kBlock), 0, s, A.n_rows, A.rowptr, A.val,
-                       A.diag, A.t_uptr, A.t_urow, A.t_lcol, A.t_nblk, X, ldx, Y, ldy, b,
+                       A.diag, A.t_row, A.t_uptr, A.t_urow, A.t_lcol, A.t_nblk, X, ldx, Y, ldy, b,
                        first ? 1 : 0, beta, P, ldp, partial);
   else
     hipLaunchKernelGGL(k_spmm_tile<false>, grid, dim3(kBlock), 0, s, A.n_rows, A.rowptr, A.val,
-                       A.diag, A.t_uptr, A.t_urow, A.t_lcol, A.t_nblk, X, ldx, Y, ldy, b,
+                       A.diag, A.t_row, A.t_uptr, A.t_urow, A.t_lcol, A.t_nblk, X, ldx, Y, ldy, b,
                        first ? 1 : 0, beta, P, ldp, partial);
   check_launch();
   return gx;

@@ -970,33 +970,64 @@ void upload_csr(const HostCSR& X, DBuf<int>& ptr, DBuf<int>& col, DBuf<double>& 
 }  // namespace
 
 // Row-block tiling of the level-0 edge form for the LDS-staged block SpMM:
-// per block of kTileRows rows, the distinct rows of X its entries gather
-// (own rows first) and each entry's position in that list.  Left off when a
-// block exceeds kTileCols distinct columns or kTileNnz entries (orderings
-// without spatial locality), so the plain kernel runs instead.
+// per block of consecutive rows, the distinct rows of X its entries gather
+// (own rows first) and each entry's position in that list.  Rows are grouped
+// greedily, a block closing before the row that would take it past
+// kTileRows rows, kTileCols distinct touched rows (own rows and columns) or
+// kTileNnz entries.  A row that alone exceeds a cap leaves the level untiled
+// (the plain kernel runs instead).
 void build_tiles(const HostCSR& W, LevelDev& D, hipStream_t s) {
   const int n = W.n_rows;
-  const int nblk = (n + kTileRows - 1) / kTileRows;
+  std::vector<int> trow{0}, stamp(n, -1);
+  {
+    int r0 = 0, touched = 0;
+    int64_t ents = 0;
+    auto add_row = [&](int r, int tile, bool count_only, int& cnt) {
+      int c = 0;
+      if (stamp[r] != tile) ++c;
+      for (int64_t q = W.ptr[r]; q < W.ptr[r + 1]; ++q)
+        if (stamp[W.col[q]] != tile) ++c;
+      if (count_only) {
+        // distinct new rows of this row alone (its columns are distinct)
+        cnt = c;
+        return;
+      }
+      stamp[r] = tile;
+      for (int64_t q = W.ptr[r]; q < W.ptr[r + 1]; ++q) stamp[W.col[q]] = tile;
+      cnt = c;
+    };
+    int tile = 0;
+    for (int r = 0; r < n; ++r) {
+      int c = 0;
+      add_row(r, tile, true, c);
+      const int64_t e = W.ptr[r + 1] - W.ptr[r];
+      if (r > r0 && (r - r0 >= kTileRows || touched + c > kTileCols || ents + e > kTileNnz)) {
+        trow.push_back(r);
+        ++tile;
+        r0 = r;
+        touched = 0;
+        ents = 0;
+        add_row(r, tile, true, c);
+      }
+      if (c > kTileCols || e > kTileNnz) return;  // one row alone exceeds a cap
+      add_row(r, tile, false, c);
+      touched += c;
+      ents += e;
+    }
+    trow.push_back(n);
+  }
+  const int nblk = static_cast<int>(trow.size()) - 1;
   std::vector<std::vector<int>> urows(nblk);
   std::vector<unsigned short> lcol(W.nnz());
-  std::vector<char> ok(nblk, 1);
 #pragma omp parallel for schedule(dynamic, 64)
   for (int t = 0; t < nblk; ++t) {
-    const int r0 = t * kTileRows, r1 = std::min(n, r0 + kTileRows);
-    if (W.ptr[r1] - W.ptr[r0] > kTileNnz) {
-      ok[t] = 0;
-      continue;
-    }
+    const int r0 = trow[t], r1 = trow[t + 1];
     std::vector<int> halo;
     for (int64_t q = W.ptr[r0]; q < W.ptr[r1]; ++q)
       if (W.col[q] < r0 || W.col[q] >= r1) halo.push_back(W.col[q]);
     std::sort(halo.begin(), halo.end());
     halo.erase(std::unique(halo.begin(), halo.end()), halo.end());
     const int own = r1 - r0;
-    if (own + static_cast<int>(halo.size()) > kTileCols) {
-      ok[t] = 0;
-      continue;
-    }
     std::vector<int>& u = urows[t];
     for (int i = r0; i < r1; ++i) u.push_back(i);
     u.insert(u.end(), halo.begin(), halo.end());
@@ -1009,15 +1040,22 @@ void build_tiles(const HostCSR& W, LevelDev& D, hipStream_t s) {
       lcol[q] = static_cast<unsigned short>(pos);
     }
   }
-  for (int t = 0; t < nblk; ++t)
-    if (!ok[t]) return;
   std::vector<int> uptr(nblk + 1, 0), urow;
-  for (int t = 0; t < nblk; ++t) uptr[t + 1] = uptr[t] + static_cast<int>(urows[t].size());
+  for (int t = 0; t < nblk; ++t) {
+    // the grouping above guarantees the caps; a block that broke one would
+    // overrun the kernel's LDS arrays, so the level would stay untiled
+    if (static_cast<int>(urows[t].size()) > kTileCols ||
+        W.ptr[trow[t + 1]] - W.ptr[trow[t]] > kTileNnz || trow[t + 1] - trow[t] > kTileRows)
+      return;
+    uptr[t + 1] = uptr[t] + static_cast<int>(urows[t].size());
+  }
   urow.reserve(uptr[nblk]);
   for (auto& u : urows) urow.insert(urow.end(), u.begin(), u.end());
+  D.t_row.upload(trow, s);
   D.t_uptr.upload(uptr, s);
   D.t_urow.upload(urow, s);
   D.t_lcol.upload(lcol, s);
+  D.A.t_row = D.t_row.p;
   D.A.t_uptr = D.t_uptr.p;
   D.A.t_urow = D.t_urow.p;
   D.A.t_lcol = D.t_lcol.p;
@@ -1025,8 +1063,8 @@ void build_tiles(const HostCSR& W, LevelDev& D, hipStream_t s) {
   MMD_HIP(hipStreamSynchronize(s));  // the host lists must outlive their copies
   const char* e = std::getenv("MMDEIG_LOG");
   if (e && std::atoi(e) != 0)
-    std::fprintf(stderr, "[mmd_build] level-0 tiles: %d blocks of %d rows, %.1f columns per block on average\n",
-                 nblk, kTileRows, static_cast<double>(uptr[nblk]) / nblk);
+    std::fprintf(stderr, "[mmd_build] level-0 tiles: %d blocks, %.1f rows and %.1f columns per block on average\n",
+                 nblk, static_cast<double>(n) / nblk, static_cast<double>(uptr[nblk]) / nblk);
 }
 
 void upload_hierarchy(mmd_handle& h, hipStream_t s) {
