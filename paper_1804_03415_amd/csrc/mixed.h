@@ -19,6 +19,12 @@ struct CsrView32 {
   const int* col = nullptr;
   const float* val = nullptr;
   const float* diag = nullptr;  // non-null: edge form y = s x + sum w (x_i - x_j)
+  // level-0 row-block tiling shared with the FP64 view (CsrView::t_*)
+  const int* t_row = nullptr;
+  const int* t_uptr = nullptr;
+  const int* t_urow = nullptr;
+  const unsigned short* t_lcol = nullptr;
+  int t_nblk = 0;
 };
 
 inline int even_ld(int b) { return (b + 1) & ~1; }

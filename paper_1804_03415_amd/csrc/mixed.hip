@@ -173,6 +173,155 @@ __global__ __launch_bounds__(kBlock) void k_spmm32_w(
   store_partials<kWave>(d0, d1, c0, b, partial);
 }
 
+// LDS-staged form on the tiled level-0 edge form, the FP32 counterpart of
+// kernels.hip's k_spmm_tile: a workgroup takes one tile (CsrView32::t_row)
+// and one 128-column slice (a lane moves two columns as a float2), issues
+// every global load of the tile in one batch (own-row streams, entries,
+// row pointers, the touched X rows), stages them in LDS and forms each row
+// from LDS.  32 KB of staged rows + 4.6 KB: four workgroups per CU.
+__global__ __launch_bounds__(kBlock, 4) void k_spmm32_tile(
+    const int* __restrict__ rowptr, const float* __restrict__ val,
+    const float* __restrict__ diag, const int* __restrict__ trow,
+    const int* __restrict__ uptr, const int* __restrict__ urow,
+    const unsigned short* __restrict__ lcol, int nblk, const float* __restrict__ X, int ldx,
+    float* __restrict__ Y, int ldy, int b, int first, const double* __restrict__ beta,
+    float* __restrict__ P, int ldp, double* __restrict__ partial) {
+  constexpr int RPW = kTileRows / kWpb;  // rows per wavefront and tile
+  __shared__ float2 sx[kTileCols * kWave];  // also the partial-sum buffer at the end
+  __shared__ float sv[kTileNnz];
+  __shared__ unsigned short sc[kTileNnz];
+  __shared__ int sp[kTileRows + 1];
+  static_assert(sizeof(sx) >= 2 * kBlock * sizeof(double), "partials reuse the staging");
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int c0 = blockIdx.y * 2 * kWave;
+  const int c = c0 + 2 * lane;
+  const bool ok0 = c < b, ok1 = c + 1 < b;
+  const int cx = ok0 ? c : 0;  // lanes past b read column 0 and store nothing
+  const float bt0 = (!first && ok0) ? static_cast<float>(beta[c]) : 0.f;
+  const float bt1 = (!first && ok1) ? static_cast<float>(beta[c + 1]) : 0.f;
+  double d0 = 0.0, d1 = 0.0;
+  const int nx = (gridDim.x % 8 == 0) ? 8 : 1;
+  const int bpx = gridDim.x / nx;
+  const int xcd = blockIdx.x % nx, bl = blockIdx.x / nx;
+  const int tpx = (nblk + nx - 1) / nx;
+  const int thi = min(nblk, (xcd + 1) * tpx);
+  for (int t = xcd * tpx + bl; t < thi; t += bpx) {
+    const int r0 = trow[t], r1 = trow[t + 1];
+    const int u0 = uptr[t], nu = uptr[t + 1] - u0;
+    const int e0 = rowptr[r0], ne = rowptr[r1] - e0;
+    float2 yo[RPW], po[RPW];
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) {
+      const int i = r0 + wid + k * kWpb;
+      const bool ok = !first && i < r1;
+      const size_t ri = (size_t)(ok ? i : 0);
+      yo[k] = ok ? ld2(Y + ri * ldy + cx) : make_float2(0.f, 0.f);
+      po[k] = ok ? ld2(P + ri * ldp + cx) : make_float2(0.f, 0.f);
+    }
+    {
+      constexpr int EPT = kTileNnz / kBlock;  // entries per thread
+      float ev[EPT];
+      unsigned short ec[EPT];
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const int e = threadIdx.x + q * kBlock;
+        ev[q] = e < ne ? val[e0 + e] : 0.f;
+        ec[q] = e < ne ? lcol[e0 + e] : 0;
+      }
+      const int rp = threadIdx.x <= r1 - r0 ? rowptr[r0 + threadIdx.x] - e0 : 0;
+      constexpr int SPW = kTileCols / kWpb;  // slots per wavefront
+      const int myu = wid + kWpb * lane;
+      const int ridx = (lane < SPW && myu < nu) ? urow[u0 + myu] : -1;
+      float2 v[SPW];
+#pragma unroll
+      for (int q = 0; q < SPW; ++q) {
+        const int j = __builtin_amdgcn_readlane(ridx, q);
+        v[q] = j >= 0 ? ld2(X + (size_t)j * ldx + cx) : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const int e = threadIdx.x + q * kBlock;
+        if (e < ne) {
+          sv[e] = ev[q];
+          sc[e] = ec[q];
+        }
+      }
+      if (threadIdx.x <= r1 - r0) sp[threadIdx.x] = rp;
+#pragma unroll
+      for (int q = 0; q < SPW; ++q) {
+        const int u = wid + kWpb * q;
+        if (u < nu) sx[u * kWave + lane] = v[q];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) {
+      const int i = r0 + wid + k * kWpb;
+      if (i < r1) {
+        const int l = i - r0;
+        const float2 xi = sx[l * kWave + lane];
+        const int lo = sp[l], hi = sp[l + 1];
+        float ax = 0.f, ay = 0.f;
+        for (int base = 0; base < hi - lo; base += kWave) {
+          const int m = min(kWave, hi - lo - base);
+          const int jv = lane < m ? static_cast<int>(sc[lo + base + lane]) : 0;
+          const float wv = lane < m ? sv[lo + base + lane] : 0.f;
+          for (int k0 = 0; k0 < m; k0 += 8) {
+            float2 xs[8];
+            float ws[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const int j = __builtin_amdgcn_readlane(jv, k0 + q);
+              ws[q] = readlane_f(wv, k0 + q);
+              xs[q] = sx[j * kWave + lane];
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              ax += ws[q] * (xi.x - xs[q].x);
+              ay += ws[q] * (xi.y - xs[q].y);
+            }
+          }
+        }
+        if (ok0) {
+          const float dg = diag[i];
+          float yx = dg * xi.x + ax, yy = dg * xi.y + ay;
+          float px, py;
+          if (first) {
+            px = xi.x;
+            py = xi.y;
+          } else {
+            yx += bt0 * yo[k].x;
+            yy += bt1 * yo[k].y;
+            px = xi.x + bt0 * po[k].x;
+            py = xi.y + bt1 * po[k].y;
+          }
+          if (!ok1) {
+            py = 0.f;
+            yy = 0.f;
+          }
+          *reinterpret_cast<float2*>(P + (size_t)i * ldp + c) = make_float2(px, py);
+          *reinterpret_cast<float2*>(Y + (size_t)i * ldy + c) = make_float2(yx, yy);
+          d0 += static_cast<double>(px) * yx;
+          d1 += static_cast<double>(py) * yy;
+        }
+      }
+    }
+    __syncthreads();  // the next tile overwrites the staging
+  }
+  double* red = reinterpret_cast<double*>(sx);
+  red[wid * kWave + lane] = d0;
+  red[kBlock + wid * kWave + lane] = d1;
+  __syncthreads();
+  if (threadIdx.x < 2 * kWave) {
+    const int l = threadIdx.x >> 1, h = threadIdx.x & 1;
+    double tsum = 0.0;
+    for (int w = 0; w < kWpb; ++w) tsum += red[h * kBlock + w * kWave + l];
+    const int cc = c0 + 2 * l + h;
+    if (cc < b) partial[(size_t)blockIdx.x * b + cc] = tsum;
+  }
+}
+
 // Narrow form: L lanes per row (2L columns per tile), R = 64 / L rows per
 // wavefront, direct index loads, four gathers in flight per lane.
 template <int L, bool EDGE>
@@ -390,6 +539,16 @@ int spmm32_cg(const CsrView32& A, const float* X, int ldx, float* Y, int ldy, in
   if (b <= 16) return launch_n<8>(A, X, ldx, Y, ldy, b, first, beta, P, ldp, partial, s);
   if (b <= 32) return launch_n<16>(A, X, ldx, Y, ldy, b, first, beta, P, ldp, partial, s);
   if (b <= 64) return launch_n<32>(A, X, ldx, Y, ldy, b, first, beta, P, ldp, partial, s);
+  if (A.t_uptr && A.t_row && A.diag) {
+    int gx = std::min(A.t_nblk, kRedBlocks);
+    if (gx >= 8) gx = gx / 8 * 8;
+    dim3 grid(gx, ceil_div(b, 2 * kWave));
+    hipLaunchKernelGGL(k_spmm32_tile, grid, dim3(kBlock), 0, s, A.rowptr, A.val, A.diag,
+                       A.t_row, A.t_uptr, A.t_urow, A.t_lcol, A.t_nblk, X, ldx, Y, ldy, b,
+                       first ? 1 : 0, beta, P, ldp, partial);
+    check_launch();
+    return gx;
+  }
   int gx = std::max(1, std::min(kRedBlocks, ceil_div(A.n_rows, 2 * kWpb)));
   if (gx >= 8) gx = gx / 8 * 8;
   dim3 grid(gx, ceil_div(b, 2 * kWave));
