@@ -354,7 +354,8 @@ def swissroll_run(a):
     p = workloads.swissroll(20000, seed=0)
     A = p.scipy()
     t = time.perf_counter()
-    dec = Decomposition.from_problem(p, levels=K, eps1=1e-5, eta=eta, cbound=20.0, r_hops=5)
+    dec = Decomposition.from_problem(p, levels=K, eps1=1e-5, eta=eta, cbound=20.0, r_hops=5,
+                                     r_hops_coarse=1)
     t_build = time.perf_counter() - t
     info = dec.info()
     print("swissroll: n %d nnz %d, levels %s, eps %s, build %.1f s" % (

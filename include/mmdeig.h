@@ -74,11 +74,14 @@ typedef struct {
                               eps(P) delta(P) <= cbound, instead of targets.
                               Patches grow from Morton-ordered seeds, trying
                               the adjacent vertex of largest total coupling
-                              sum |a_vp| first; the localised Psi then needs a
-                              radius r_hops that keeps the level accurate to
-                              eps_k (5 on the SwissRoll graph of Section 7.1) [0] */
+                              sum |a_vp| first, with the split patch energy
+                              A[P,P] - diag(sum_{j not in P} |a_ij|) on every
+                              level; the localised Psi then needs a radius
+                              r_hops that keeps the level accurate to eps_k
+                              (5 on the SwissRoll graph of Section 7.1) [0] */
   double eta;              /* ratio eps_k / eps_(k+1) [0.1]                      */
   double cbound;           /* condition bound c [20]                             */
+  int32_t r_hops_coarse;   /* localisation radius of Psi^(k), k >= 2 [r_hops]    */
 } mmd_build_opts;
 
 /* Solver options (Section 5 parameter choice).  Zero fields take defaults. */

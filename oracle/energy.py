@@ -21,6 +21,14 @@ inherited elements (Definition 2.4) are spread over several coarse patches by
 the overlap of the localized Psi, so almost no element is interior to a small
 coarse patch.  Patches of the second and later levels therefore use the
 closed energy, the principal submatrix A^(k)[P, P] (always SPD).
+
+The partition to prescribed accuracy uses the split energy instead, on
+every level: E_P = A[P, P] - diag(sum_{j not in P} |a_ij|).  The rest,
+A - sum_P E_P, is the off-patch part plus the diagonal of its absolute row
+sums, which is diagonally dominant and so positive semidefinite; hence
+sum_P E_P <= A, the property the patch error bound of Section 2.2 needs.  On
+level 0 of a Laplacian plus a nonnegative diagonal it equals the interior
+energy.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -90,4 +98,25 @@ def closed_energy(A: sp.csr_matrix, members: np.ndarray) -> np.ndarray:
             b = pos.get(int(c))
             if b is not None:
                 E[a, b] = v
+    return E
+
+
+def split_energy(A: sp.csr_matrix, members: np.ndarray) -> np.ndarray:
+    """E_P = A[P, P] - diag(sum_{j not in P} |a_ij|) for the (sorted) vertex
+    list members: sum over patches of E_P is bounded by A (Section 2.2 patch
+    energy; see the module docstring)."""
+    members = np.asarray(members, dtype=np.int64)
+    pos = {int(v): a for a, v in enumerate(members)}
+    p = members.size
+    E = np.zeros((p, p))
+    for a, i in enumerate(members):
+        lo, hi = A.indptr[i], A.indptr[i + 1]
+        outside = 0.0
+        for c, v in zip(A.indices[lo:hi], A.data[lo:hi]):
+            b = pos.get(int(c))
+            if b is None:
+                outside += abs(v)
+            else:
+                E[a, b] = v
+        E[a, a] -= outside
     return E

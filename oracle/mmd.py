@@ -7,7 +7,8 @@ Per level k >= 1, from the level-(k-1) matrix A^(k-1) (A^(0) = A, M^(0) = I):
   2. phi_j = unit eigenvector of the smallest eigenvalue of the patch's
      energy (q = 1, Section 2.2), sign: sum(phi_j) > 0; the patch error
      factor is 1 / lambda_2(patch energy) (Section 2.2).  Patch energy:
-     interior energy on level 1, closed energy on levels >= 2 (energy.py);
+     interior energy on level 1, closed energy on levels >= 2; the split
+     energy on every level of a partition to prescribed accuracy (energy.py);
   3. U_j = the complement of phi_j inside the patch, realised as columns
      2..|P_j| of one Householder reflector H_j with H_j e_1 = +-phi_j
      (Lemma 2.3 remark: QR completion gives kappa(U^T U) = 1);
@@ -31,7 +32,7 @@ import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
 
-from .energy import closed_energy, energy_elements, interior_energy
+from .energy import closed_energy, energy_elements, interior_energy, split_energy
 
 
 # ----------------------------------------------------------------------------
@@ -147,8 +148,17 @@ def greedy_partition(A: sp.csr_matrix, coords: Optional[np.ndarray], target: int
     return out
 
 
+def patch_energy(A: sp.csr_matrix, members, energy: str) -> np.ndarray:
+    """The patch energy named by `energy`: "interior", "closed" or "split"."""
+    if energy == "closed":
+        return closed_energy(A, members)
+    if energy == "split":
+        return split_energy(A, members)
+    return interior_energy(A, members)
+
+
 def eps_partition(A: sp.csr_matrix, coords: Optional[np.ndarray], eps_k: float, cbound: float,
-                  closed: bool, max_size: int = 32):
+                  energy: str = "split", max_size: int = 32):
     """Partition with prescribed accuracy (Section 2.3: the partition must give
     error factor eps(P) <= eps_k and eps(P) delta(P) <= c; reading of the
     deferred partitioner).
@@ -158,7 +168,8 @@ def eps_partition(A: sp.csr_matrix, coords: Optional[np.ndarray], eps_k: float, 
     patch and not yet refused by it, the one with the largest total coupling
     sum_{p in P} |a_vp| to the patch is tried next (ties: smaller vertex id).
     It joins when the enlarged patch still has eps(P) = 1 / lambda_2(E_P) <=
-    eps_k (E_P the interior energy on level 1, the closed energy above) and
+    eps_k (E_P the patch energy named by `energy`, the split energy in the
+    decomposition) and
     eps(P) delta(P) <= c with delta(P) = 1 / (phi^T Abar_P^-1 phi), phi the
     unit eigenvector of lambda_1(E_P) and Abar_P the closed energy (principal
     submatrix); otherwise the patch refuses it.  The patch closes when no
@@ -194,7 +205,7 @@ def eps_partition(A: sp.csr_matrix, coords: Optional[np.ndarray], eps_k: float, 
             u = min(cands)[1]
             cand = np.sort(np.asarray(members + [u], dtype=np.int64))
             Abar = A[cand][:, cand].toarray()  # closed energy: principal submatrix
-            E = Abar if closed else interior_energy(A, cand)
+            E = patch_energy(A, cand, energy)
             w, V = np.linalg.eigh(0.5 * (E + E.T))
             ok = False
             if w[1] > 0:
@@ -253,13 +264,16 @@ def hop_set(nbrs, j, r):
 # per-patch basis, Householder complement, Psi
 # ----------------------------------------------------------------------------
 
-def local_basis(A: sp.csr_matrix, members, closed=False):
+def local_basis(A: sp.csr_matrix, members, closed=False, energy=None):
     """phi (unit, sum > 0; first nonzero > 0 if the sum vanishes), lambda_1, lambda_2.
 
     The patch energy is the interior energy on the first level and the closed
-    energy (principal submatrix) on later levels.
+    energy (principal submatrix) on later levels, or the split energy on every
+    level of a partition to prescribed accuracy (`energy` names it).
     """
-    E = closed_energy(A, members) if closed else interior_energy(A, members)
+    if energy is None:
+        energy = "closed" if closed else "interior"
+    E = patch_energy(A, members, energy)
     E = 0.5 * (E + E.T)
     w, V = np.linalg.eigh(E)
     phi = V[:, 0].copy()
@@ -436,6 +450,7 @@ def gershgorin_max(M: Optional[sp.csr_matrix]) -> float:
 
 def build_mmd(A, coords=None, grid=None, levels=3, targets=(4, 8), grid_blocks=(4, 2),
               r_hops=1, exact_max_n=0, min_coarse=4, eps1=0.0, eta=0.1, cbound=20.0,
+              r_hops_coarse=0,
               max_patch=32):
     """Build the K-level decomposition.
 
@@ -444,6 +459,7 @@ def build_mmd(A, coords=None, grid=None, levels=3, targets=(4, 8), grid_blocks=(
     targets     greedy patch size per level for graphs (last entry repeats)
     grid_blocks tensor block edge per level for structured grids (last repeats)
     r_hops      localisation radius of Psi in patch hops
+    r_hops_coarse  radius of Psi^(k) for k >= 2 (0: r_hops)
     exact_max_n levels with N_{k-1} <= exact_max_n use the exact Psi
     eps1, eta, cbound, max_patch
                 eps1 > 0: graphs are partitioned to prescribed accuracy,
@@ -464,7 +480,7 @@ def build_mmd(A, coords=None, grid=None, levels=3, targets=(4, 8), grid_blocks=(
             blk = grid_blocks[min(k - 1, len(grid_blocks) - 1)]
             patches, cgrid = grid_partition(prev.grid, blk)
         elif eps1 > 0:
-            patches = eps_partition(Ak, prev.coords, eps1 / eta ** (k - 1), cbound, k >= 2,
+            patches = eps_partition(Ak, prev.coords, eps1 / eta ** (k - 1), cbound, "split",
                                     max_patch)
             cgrid = None
         else:
@@ -475,14 +491,16 @@ def build_mmd(A, coords=None, grid=None, levels=3, targets=(4, 8), grid_blocks=(
             break
         phis, hh, epsp = [], [], []
         for mem in patches:
-            phi, l1, l2 = local_basis(Ak, mem, closed=(k >= 2))
+            phi, l1, l2 = local_basis(Ak, mem, energy=("split" if eps1 > 0 else
+                                                       "closed" if k >= 2 else "interior"))
             phis.append(phi)
             hh.append(householder_vector(phi))
             epsp.append(0.0 if len(mem) < 2 else (1.0 / l2 if l2 > 0 else np.inf))
         if prev.n <= exact_max_n:
             Psi = psi_exact(Ak, patches, phis)
         else:
-            Psi = psi_localized(Ak, patches, phis, r_hops)
+            Psi = psi_localized(Ak, patches, phis,
+                                r_hops_coarse if (k >= 2 and r_hops_coarse > 0) else r_hops)
         # the support of psi_j is the set of its nonzero entries: a stored exact
         # zero carries no coupling into the Galerkin patterns
         Psi.eliminate_zeros()

@@ -38,7 +38,8 @@ class mmd_build_opts(ctypes.Structure):
                 ("grid_blocks", ctypes.c_int32 * 8), ("r_hops", ctypes.c_int32),
                 ("exact_max_n", ctypes.c_int64), ("min_coarse", ctypes.c_int32),
                 ("max_patch", ctypes.c_int32), ("eps1", ctypes.c_double),
-                ("eta", ctypes.c_double), ("cbound", ctypes.c_double)]
+                ("eta", ctypes.c_double), ("cbound", ctypes.c_double),
+                ("r_hops_coarse", ctypes.c_int32)]
 
 
 class eig_opts(ctypes.Structure):

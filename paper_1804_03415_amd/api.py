@@ -26,12 +26,14 @@ def _close_all():
 
 
 def build_options(levels=3, targets=(4, 8), grid_blocks=(4, 2), r_hops=1, exact_max_n=0,
-                  min_coarse=4, eps1=0.0, eta=0.1, cbound=20.0, max_patch=32):
+                  min_coarse=4, eps1=0.0, eta=0.1, cbound=20.0, max_patch=32,
+                  r_hops_coarse=0):
     """mmd_build_opts; eps1 > 0 partitions graphs to prescribed accuracy
     (eps(P^(k)) <= eps1 / eta^(k-1), eps delta <= cbound) instead of the
     target patch sizes."""
     o = mmd_build_opts()
     o.eps1, o.eta, o.cbound, o.max_patch = eps1, eta, cbound, max_patch
+    o.r_hops_coarse = r_hops_coarse
     o.levels = levels if levels > 0 else -1
     o.n_targets = len(targets)
     for i, t in enumerate(targets):

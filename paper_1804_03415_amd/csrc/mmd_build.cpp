@@ -180,9 +180,16 @@ Patches greedy_patches(const HostCSR& A, const std::vector<double>& xyz, int d, 
 }
 
 // ---------------------------------------------------------------- patch energies
-// Interior energy (level 1, generalised edges inside P + clamped remainder)
-// or closed energy (levels >= 2, principal submatrix).
-std::vector<double> patch_energy(const HostCSR& A, const std::vector<int>& mem, bool closed) {
+// Patch energies (Section 2.2): interior (level 1 of a target-size
+// partition: generalised edges inside P + clamped remainder), closed
+// (its levels >= 2: the principal submatrix), or split (every level of a
+// partition to prescribed accuracy: A[P, P] - diag(sum_{j not in P} |a_ij|),
+// whose sum over patches is bounded by A because the rest is diagonally
+// dominant).
+enum class Energy { Interior, Closed, Split };
+
+std::vector<double> patch_energy(const HostCSR& A, const std::vector<int>& mem, Energy kind) {
+  const bool closed = kind == Energy::Closed;
   const int p = static_cast<int>(mem.size());
   std::vector<double> E((size_t)p * p, 0.0);
   for (int a = 0; a < p; ++a) {
@@ -202,7 +209,9 @@ std::vector<double> patch_energy(const HostCSR& A, const std::vector<int>& mem, 
         inner += std::fabs(v);
       }
     }
-    E[(size_t)a * p + a] = closed ? diag : inner + std::max(diag - offabs, 0.0);
+    E[(size_t)a * p + a] = closed                   ? diag
+                           : kind == Energy::Split ? diag - (offabs - inner)
+                                                   : inner + std::max(diag - offabs, 0.0);
   }
   return E;
 }
@@ -213,14 +222,14 @@ std::vector<double> patch_energy(const HostCSR& A, const std::vector<int>& mem, 
 // vertices adjacent to the patch and not yet refused by it, the one with the
 // largest total coupling sum_{p in P} |a_vp| to the patch is tried next (ties:
 // smaller vertex id).  It joins when the enlarged patch keeps
-// eps(P) = 1 / lambda_2(E_P) <= eps_k (E_P the patch energy of the level) and
+// eps(P) = 1 / lambda_2(E_P) <= eps_k (E_P the split patch energy) and
 // eps(P) delta(P) <= c, where delta(P) = 1 / (phi^T Abar_P^-1 phi) with phi
 // the eigenvector of lambda_1(E_P) and Abar_P the principal submatrix;
 // otherwise the patch refuses it.  The patch closes when no candidate is left
 // or it holds max_size vertices.  Couplings accumulate member by member in
 // join order and CSR order within a row.
 Patches eps_patches(const HostCSR& A, const std::vector<double>& xyz, int d, double eps_k,
-                    double cbound, bool closed, int max_size) {
+                    double cbound, Energy energy, int max_size) {
   const int n = A.n_rows;
   std::vector<int> order;
   if (d > 0) order = morton_order(xyz, n, d);
@@ -262,12 +271,12 @@ Patches eps_patches(const HostCSR& A, const std::vector<double>& xyz, int d, dou
       cand.push_back(u);
       std::sort(cand.begin(), cand.end());
       const int p = static_cast<int>(cand.size());
-      const std::vector<double> E = patch_energy(A, cand, closed);
+      const std::vector<double> E = patch_energy(A, cand, energy);
       std::vector<double> w, Z;
       dense::sym_eig(p, E.data(), w, &Z);
       bool ok = false;
       std::vector<double> R;
-      const std::vector<double> Ab = patch_energy(A, cand, true);
+      const std::vector<double> Ab = patch_energy(A, cand, Energy::Closed);
       if (w[1] > 0.0 && dense::cholesky_upper(p, Ab.data(), R)) {
         const double eps = 1.0 / w[1];
         // phi^T Abar^-1 phi by Cholesky of the principal submatrix
@@ -847,7 +856,8 @@ void build_hierarchy(mmd_handle& h, const mmd_csr& in, const mmd_build_opts& o) 
       const double eta = o.eta > 0 ? o.eta : 0.1;
       const double cb = o.cbound > 0 ? o.cbound : 20.0;
       const int mx = o.max_patch > 0 ? o.max_patch : 32;
-      P = eps_patches(Ak, prev.coords, prev.cdim, o.eps1 / std::pow(eta, k - 1), cb, k >= 2, mx);
+      P = eps_patches(Ak, prev.coords, prev.cdim, o.eps1 / std::pow(eta, k - 1), cb,
+                      Energy::Split, mx);
     } else {
       const int tgt = targets[std::min<size_t>(k - 1, targets.size() - 1)];
       P = greedy_patches(Ak, prev.coords, prev.cdim, tgt);
@@ -866,7 +876,7 @@ void build_hierarchy(mmd_handle& h, const mmd_csr& in, const mmd_build_opts& o) 
     L.hh_u.assign(L.members.size(), 0.0);
     L.hh_scale.assign(np, 0.0);
     L.eps_patch.assign(np, 0.0);
-    const bool closed = k >= 2;
+    const Energy ekind = o.eps1 > 0 ? Energy::Split : k >= 2 ? Energy::Closed : Energy::Interior;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int j = 0; j < np; ++j) {
       const int p = static_cast<int>(P[j].size());
@@ -875,7 +885,7 @@ void build_hierarchy(mmd_handle& h, const mmd_csr& in, const mmd_build_opts& o) 
         L.phi[off] = 1.0;
         L.eps_patch[j] = 0.0;
       } else {
-        std::vector<double> E = patch_energy(Ak, P[j], closed);
+        std::vector<double> E = patch_energy(Ak, P[j], ekind);
         std::vector<double> w, Z;
         dense::sym_eig(p, E.data(), w, &Z);
         double sum = 0.0;
@@ -922,7 +932,8 @@ void build_hierarchy(mmd_handle& h, const mmd_csr& in, const mmd_build_opts& o) 
     if (prev.n <= o.exact_max_n)
       L.Psi = psi_exact(Ak, P, L.phi, L.patch_ptr);
     else
-      L.Psi = psi_localized(Ak, P, L.phi, L.patch_ptr, r_hops);
+      L.Psi = psi_localized(Ak, P, L.phi, L.patch_ptr,
+                            k >= 2 && o.r_hops_coarse > 0 ? o.r_hops_coarse : r_hops);
     drop_zeros(L.Psi);
     L.A = galerkin(L.Psi, &Ak);
     L.M = galerkin(L.Psi, k == 1 ? nullptr : &prev.M);

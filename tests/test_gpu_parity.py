@@ -114,6 +114,33 @@ def test_build_parity(built):
             assert abs(X - ref).max() <= 1e-11 * abs(ref).max()
 
 
+def _export(dec, k, which):
+    rp, ci, v, shape = dec.export(k, which)
+    return sp.csr_matrix((v, ci, rp), shape=shape)
+
+
+def spmv_bar(A, X, ref):
+    """1e-12 max|ref|, or the rounding bound of length-m dot products,
+    gamma_m |A| |X| with m the longest stored row (Higham's gamma_m = m u /
+    (1 - m u), doubled for two summation orders), whichever is larger: dense
+    coarse rows (hundreds of entries) sum with cancellation."""
+    A = sp.csr_matrix(A)
+    m = int(np.diff(A.indptr).max()) if A.nnz else 1
+    u = 2.0 ** -53
+    return np.maximum(1e-12 * np.abs(ref).max(), 2 * m * u / (1 - m * u) * (abs(A) @ np.abs(X)))
+
+
+def solve_floor(A, X, B):
+    """Attainable accuracy of a recursive-residual Krylov solve, relative to
+    ||b||: c u ||A|| ||x|| with c = 50, or 5 m for rows of m entries (each
+    product's rounding grows with the row length)."""
+    A = sp.csr_matrix(A)
+    m = int(np.diff(A.indptr).max()) if A.nnz else 1
+    c = max(50.0, 5.0 * m)
+    return c * 2.2e-16 * sla.norm(A.toarray(), 2) * np.linalg.norm(X, axis=0) / np.linalg.norm(
+        B, axis=0)
+
+
 def test_level_operators(built, torch_cuda):
     torch = torch_cuda
     p, kw, dec, M = built
@@ -123,10 +150,18 @@ def test_level_operators(built, torch_cuda):
         X = wl.random_block(lev.n, b, seed=k)
         refA = krylov.EdgeForm(p.scipy()) @ X if k == 0 else lev.A @ X
         Y = dec.apply(k, "A", _t(torch, X)).cpu().numpy()
-        assert np.abs(Y - refA).max() <= 1e-12 * np.abs(refA).max()
+        # the kernel against the library's own matrix (rounding bound), and
+        # against the oracle's matrix at the build-parity bar (coarse entries
+        # agree to 1e-11 of the largest: their local solves are ill conditioned)
+        Alib = p.scipy() if k == 0 else _export(dec, k, 0)
+        assert np.all(np.abs(Y - Alib @ X) <= spmv_bar(Alib, X, Alib @ X))
+        assert np.abs(Y - refA).max() <= 1e-11 * np.abs(refA).max()
         if k >= 1:
             Y = dec.apply(k, "M", _t(torch, X)).cpu().numpy()
-            assert np.abs(Y - lev.M @ X).max() <= 1e-12 * np.abs(lev.M @ X).max()
+            Mlib = _export(dec, k, 1)
+            assert np.all(np.abs(Y - Mlib @ X) <= spmv_bar(Mlib, X, Mlib @ X))
+            refM = lev.M @ X
+            assert np.abs(Y - refM).max() <= 1e-11 * np.abs(refM).max()
         if k < M.K:
             up = M.levels[k + 1]
             Y = dec.apply(k, "Ut", _t(torch, X)).cpu().numpy()
@@ -142,8 +177,10 @@ def test_level_operators(built, torch_cuda):
             assert np.abs(Y - ref).max() <= 1e-12 * np.abs(ref).max()
             Xc = wl.random_block(up.n, b, seed=20 + k)
             Y = dec.apply(k, "Psi", _t(torch, Xc)).cpu().numpy()
+            Plib = _export(dec, k + 1, 2)
+            assert np.all(np.abs(Y - Plib @ Xc) <= spmv_bar(Plib, Xc, Plib @ Xc))
             ref = up.Psi @ Xc
-            assert np.abs(Y - ref).max() <= 1e-12 * np.abs(ref).max()
+            assert np.abs(Y - ref).max() <= 1e-11 * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("b", [33, 64, 130, 300])
@@ -198,7 +235,7 @@ def test_level_solves(built, torch_cuda, b):
         # true residual within the solver's stop rule plus the attainable FP64
         # accuracy of a recursive-residual Krylov method, c u ||A|| ||x|| / ||b||
         nb = np.linalg.norm(rhs, axis=0)
-        floor = 50 * 2.2e-16 * np.linalg.norm(Ad, 2) * np.linalg.norm(X, axis=0) / nb
+        floor = solve_floor(p.scipy() if k == 0 else lev.A, X, rhs)
         res = np.linalg.norm(rhs - Ad @ X, axis=0) / nb
         assert np.all(res <= 1.5 * tol + floor)
         Aop = krylov.EdgeForm(p.scipy()) if k == 0 else lev.A
@@ -216,7 +253,7 @@ def test_level_solves(built, torch_cuda, b):
             G, it = dec.solve(k, 1, _t(torch, r2), tol=tol)
             G = G.cpu().numpy()
             nb2 = np.linalg.norm(r2, axis=0)
-            floor = 50 * 2.2e-16 * np.linalg.norm(B, 2) * np.linalg.norm(G, axis=0) / nb2
+            floor = solve_floor(sp.csr_matrix(B), G, r2)
             res = np.linalg.norm(r2 - B @ G, axis=0) / nb2
             assert np.all(res <= 1.5 * tol + floor)
 

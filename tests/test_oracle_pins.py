@@ -594,7 +594,7 @@ def test_eps_partition_meets_its_bounds():
         for mem in lev.patches:
             if len(mem) < 2:
                 continue
-            E = energy.closed_energy(prev.A, mem) if k >= 2 else energy.interior_energy(prev.A, mem)
+            E = energy.split_energy(prev.A, mem)
             w, V = np.linalg.eigh(E)
             eps = 1.0 / w[1]
             Abar = prev.A[mem][:, mem].toarray()
@@ -635,5 +635,5 @@ def test_eps_partition_full_roll_level1_size():
     level-1 dofs (decomposition table of Section 7.2); this partition reading
     gives a level-1 size within 2% of it."""
     p = wl.swissroll(20000, seed=0)
-    P = mm.eps_partition(p.scipy(), p.coords, 1e-5, 20.0, False, 32)
+    P = mm.eps_partition(p.scipy(), p.coords, 1e-5, 20.0, "split", 32)
     assert abs(len(P) - 5528) <= 0.02 * 5528
