@@ -506,10 +506,11 @@ def main():
     traffic = a.traffic_bytes if a.traffic_bytes is not None else (
         None if fp32 else measured_traffic())
     roof = {"bound": "hbm",
-            "kernel": ("k_spmm32_w<edge>: level-0 FP32 block-CG step" if fp32 else
-                       "k_spmm_tile<fuse> (LDS-staged 32-row tiles; k_spmm_r64 when the "
-                       "level is not tiled): level-0 block-CG step P = R + beta P, "
-                       "Q = A R + beta Q, partial p.q") + " (block width %d..1)" % a.nev,
+            "kernel": ("k_spmm32_tile: level-0 FP32 block-CG step (LDS-staged tiles)" if fp32 else
+                       "k_spmm_tile<fuse> (LDS-staged tiles of up to 32 rows touching up to "
+                       "64 rows; k_spmm_r64 when the level is not tiled): level-0 block-CG "
+                       "step P = R + beta P, Q = A R + beta Q, partial p.q") +
+                      " (block width %d..1)" % a.nev,
             "achieved": kr["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": kr["frac"], "traffic": traffic,
             "bytes_per_launch": kr["bytes_per_launch"], "launches": kr["launches"],
@@ -536,7 +537,7 @@ def main():
                  "per_pair": {"rel_residual": [float("%.3g" % x) for x in rho_m],
                               "rel_eig_err_vs_fp64": [float("%.3g" % x) for x in e_m],
                               "cluster_angle_vs_fp64": [float("%.3g" % x) for x in ang_pp]},
-                 "kernel": "k_spmm32_w<edge>: level-0 FP32 block-CG step",
+                 "kernel": "k_spmm32_tile: level-0 FP32 block-CG step (LDS-staged tiles)",
                  "kernel_achieved_GBs": krm["achieved"], "kernel_frac": krm["frac"],
                  "kernel_avg_launch_us": krm["avg_launch_us"],
                  "kernel_launches": krm["launches"]}
