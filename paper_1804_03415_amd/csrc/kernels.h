@@ -20,12 +20,14 @@ struct CsrView {
   const double* val = nullptr;
   const double* diag = nullptr;  // non-null: edge form y = s x + sum w (x_i - x_j)
   double avg_row = 1.0;
-  // Row-block tiling of the edge form (level 0; t_uptr == nullptr: none).
-  // Block t owns rows [t_row[t], t_row[t + 1]) (at most kTileRows); its
-  // column set U_t lists those rows first, in order, then the other columns
-  // its rows touch, ascending: t_urow[t_uptr[t] .. t_uptr[t + 1]).  t_lcol[q]
-  // is the position in U_t of col[q].  Every |U_t| <= kTileCols and every
-  // block holds at most kTileNnz entries.
+  // Row-block tiling of the edge form (level 0; t_uptr == nullptr: none),
+  // built for tile shape kTileShapes[t_kind].  Block t owns rows
+  // [t_row[t], t_row[t + 1]) (at most shape.rows); its column set U_t lists
+  // those rows first, in order, then the other columns its rows touch,
+  // ascending: t_urow[t_uptr[t] .. t_uptr[t + 1]).  t_lcol[q] is the position
+  // in U_t of col[q].  Every |U_t| <= shape.cols and every block holds at
+  // most shape.nnz entries.
+  int t_kind = 0;
   const int* t_row = nullptr;
   const int* t_uptr = nullptr;
   const int* t_urow = nullptr;
@@ -33,9 +35,17 @@ struct CsrView {
   int t_nblk = 0;
 };
 
-constexpr int kTileRows = 32;   // max rows per tile block
-constexpr int kTileCols = 64;   // max distinct columns (gathered rows) per block
-constexpr int kTileNnz = 768;   // max entries per block
+// Tile shapes of the LDS-staged SpMMs: max rows per block, max distinct
+// gathered rows (staged in LDS), max entries, and the workgroups per CU the
+// LDS and register budget allow.  The level-0 tiling picks one per matrix by
+// timing (build-time autotuning).
+struct TileShape {
+  int rows, cols, nnz, wgs_per_cu;
+};
+constexpr int kNumTileShapes = 3;
+constexpr TileShape kTileShapes[kNumTileShapes] = {
+    {32, 80, 1024, 3}, {32, 64, 768, 4}, {16, 48, 512, 5}};
+constexpr int kTileRowsMax = 32;
 
 // Patch Householder data of one level transfer (k-1 -> k).
 struct HouseView {

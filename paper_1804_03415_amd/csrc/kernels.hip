@@ -276,8 +276,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
 }
 
 // LDS-staged block SpMM on the tiled level-0 edge form (CsrView::t_uptr):
-// a workgroup takes a tile of up to kTileRows consecutive rows whose entries
-// touch at most kTileCols rows, and one 64-column slice, copies the X rows
+// a workgroup takes a tile of up to shape.rows consecutive rows whose entries
+// touch at most shape.cols rows, and one 64-column slice, copies the X rows
 // its entries touch (own rows first, then the halo) into LDS with one
 // coalesced 512-byte load per row, together with the tile's weights, local
 // column positions and row pointers, and then forms every row from LDS.
@@ -289,8 +289,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
 // RGG in Morton order).  Tiles are dealt to the 8 XCDs in contiguous ranges,
 // so neighbouring tiles that share halo rows run on the same L2.  Fused CG
 // epilogue as in k_spmm_r64.
-template <bool FUSE>
-__global__ __launch_bounds__(kBlock, 4) void k_spmm_tile(
+template <bool FUSE, int KIND>
+__global__ __launch_bounds__(kBlock, kTileShapes[KIND].wgs_per_cu) void k_spmm_tile(
     int n_rows, const int* __restrict__ rowptr, const double* __restrict__ val,
     const double* __restrict__ diag, const int* __restrict__ trow,
     const int* __restrict__ uptr, const int* __restrict__ urow,
@@ -299,6 +299,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_spmm_tile(
     const double* __restrict__ beta, double* __restrict__ P, int ldp,
     double* __restrict__ partial) {
   constexpr int WPB = kBlock / kWave;
+  constexpr int kTileRows = kTileShapes[KIND].rows;
+  constexpr int kTileCols = kTileShapes[KIND].cols;
+  constexpr int kTileNnz = kTileShapes[KIND].nnz;
   constexpr int RPW = kTileRows / WPB;  // rows per wavefront and tile
   __shared__ double sx[kTileCols * kWave];  // also the partial-sum buffer at the end
   __shared__ double sv[kTileNnz];
@@ -432,6 +435,20 @@ __global__ __launch_bounds__(kBlock, 4) void k_spmm_tile(
   }
 }
 
+template <int KIND>
+void launch_tile_kind(const CsrView& A, const double* X, int ldx, double* Y, int ldy, int b,
+                      hipStream_t s, bool fuse, bool first, const double* beta, double* P,
+                      int ldp, double* partial, dim3 grid) {
+  if (fuse)
+    hipLaunchKernelGGL((k_spmm_tile<true, KIND>), grid, dim3(kBlock), 0, s, A.n_rows, A.rowptr,
+                       A.val, A.diag, A.t_row, A.t_uptr, A.t_urow, A.t_lcol, A.t_nblk, X, ldx, Y,
+                       ldy, b, first ? 1 : 0, beta, P, ldp, partial);
+  else
+    hipLaunchKernelGGL((k_spmm_tile<false, KIND>), grid, dim3(kBlock), 0, s, A.n_rows, A.rowptr,
+                       A.val, A.diag, A.t_row, A.t_uptr, A.t_urow, A.t_lcol, A.t_nblk, X, ldx, Y,
+                       ldy, b, first ? 1 : 0, beta, P, ldp, partial);
+}
+
 int launch_spmm_tile(const CsrView& A, const double* X, int ldx, double* Y, int ldy, int b,
                      hipStream_t s, bool fuse, bool first, const double* beta, double* P,
                      int ldp, double* partial) {
@@ -439,14 +456,11 @@ int launch_spmm_tile(const CsrView& A, const double* X, int ldx, double* Y, int 
   if (fuse && partial) gx = std::min(gx, kRedBlocks);
   if (gx >= 8) gx = gx / 8 * 8;  // whole XCD rounds
   dim3 grid(gx, ceil_div(b, kWave));
-  if (fuse)
-    hipLaunchKernelGGL(k_spmm_tile<true>, grid, dim3(kBlock), 0, s, A.n_rows, A.rowptr, A.val,
-                       A.diag, A.t_row, A.t_uptr, A.t_urow, A.t_lcol, A.t_nblk, X, ldx, Y, ldy, b,
-                       first ? 1 : 0, beta, P, ldp, partial);
-  else
-    hipLaunchKernelGGL(k_spmm_tile<false>, grid, dim3(kBlock), 0, s, A.n_rows, A.rowptr, A.val,
-                       A.diag, A.t_row, A.t_uptr, A.t_urow, A.t_lcol, A.t_nblk, X, ldx, Y, ldy, b,
-                       first ? 1 : 0, beta, P, ldp, partial);
+  switch (A.t_kind) {
+    case 0: launch_tile_kind<0>(A, X, ldx, Y, ldy, b, s, fuse, first, beta, P, ldp, partial, grid); break;
+    case 1: launch_tile_kind<1>(A, X, ldx, Y, ldy, b, s, fuse, first, beta, P, ldp, partial, grid); break;
+    default: launch_tile_kind<2>(A, X, ldx, Y, ldy, b, s, fuse, first, beta, P, ldp, partial, grid); break;
+  }
   check_launch();
   return gx;
 }

@@ -20,6 +20,7 @@ struct CsrView32 {
   const float* val = nullptr;
   const float* diag = nullptr;  // non-null: edge form y = s x + sum w (x_i - x_j)
   // level-0 row-block tiling shared with the FP64 view (CsrView::t_*)
+  int t_kind = 0;
   const int* t_row = nullptr;
   const int* t_uptr = nullptr;
   const int* t_urow = nullptr;

@@ -178,14 +178,18 @@ __global__ __launch_bounds__(kBlock) void k_spmm32_w(
 // and one 128-column slice (a lane moves two columns as a float2), issues
 // every global load of the tile in one batch (own-row streams, entries,
 // row pointers, the touched X rows), stages them in LDS and forms each row
-// from LDS.  32 KB of staged rows + 4.6 KB: four workgroups per CU.
-__global__ __launch_bounds__(kBlock, 4) void k_spmm32_tile(
+// from LDS.  Same tile shapes (and workgroups per CU) as the FP64 kernel.
+template <int KIND>
+__global__ __launch_bounds__(kBlock, kTileShapes[KIND].wgs_per_cu) void k_spmm32_tile(
     const int* __restrict__ rowptr, const float* __restrict__ val,
     const float* __restrict__ diag, const int* __restrict__ trow,
     const int* __restrict__ uptr, const int* __restrict__ urow,
     const unsigned short* __restrict__ lcol, int nblk, const float* __restrict__ X, int ldx,
     float* __restrict__ Y, int ldy, int b, int first, const double* __restrict__ beta,
     float* __restrict__ P, int ldp, double* __restrict__ partial) {
+  constexpr int kTileRows = kTileShapes[KIND].rows;
+  constexpr int kTileCols = kTileShapes[KIND].cols;
+  constexpr int kTileNnz = kTileShapes[KIND].nnz;
   constexpr int RPW = kTileRows / kWpb;  // rows per wavefront and tile
   __shared__ float2 sx[kTileCols * kWave];  // also the partial-sum buffer at the end
   __shared__ float sv[kTileNnz];
@@ -543,9 +547,16 @@ int spmm32_cg(const CsrView32& A, const float* X, int ldx, float* Y, int ldy, in
     int gx = std::min(A.t_nblk, kRedBlocks);
     if (gx >= 8) gx = gx / 8 * 8;
     dim3 grid(gx, ceil_div(b, 2 * kWave));
-    hipLaunchKernelGGL(k_spmm32_tile, grid, dim3(kBlock), 0, s, A.rowptr, A.val, A.diag,
-                       A.t_row, A.t_uptr, A.t_urow, A.t_lcol, A.t_nblk, X, ldx, Y, ldy, b,
-                       first ? 1 : 0, beta, P, ldp, partial);
+#define MMD_TILE32(KIND)                                                                  \
+  hipLaunchKernelGGL(k_spmm32_tile<KIND>, grid, dim3(kBlock), 0, s, A.rowptr, A.val, A.diag, \
+                     A.t_row, A.t_uptr, A.t_urow, A.t_lcol, A.t_nblk, X, ldx, Y, ldy, b,     \
+                     first ? 1 : 0, beta, P, ldp, partial)
+    switch (A.t_kind) {
+      case 0: MMD_TILE32(0); break;
+      case 1: MMD_TILE32(1); break;
+      default: MMD_TILE32(2); break;
+    }
+#undef MMD_TILE32
     check_launch();
     return gx;
   }

@@ -983,45 +983,43 @@ void upload_csr(const HostCSR& X, DBuf<int>& ptr, DBuf<int>& col, DBuf<double>& 
 // Row-block tiling of the level-0 edge form for the LDS-staged block SpMM:
 // per block of consecutive rows, the distinct rows of X its entries gather
 // (own rows first) and each entry's position in that list.  Rows are grouped
-// greedily, a block closing before the row that would take it past
-// kTileRows rows, kTileCols distinct touched rows (own rows and columns) or
-// kTileNnz entries.  A row that alone exceeds a cap leaves the level untiled
-// (the plain kernel runs instead).
-void build_tiles(const HostCSR& W, LevelDev& D, hipStream_t s) {
+// greedily, a block closing before the row that would take it past the
+// shape's rows, distinct touched rows (own rows and columns) or entries.  A
+// row that alone exceeds a cap leaves the level untiled for that shape.
+struct TileSet {
+  std::vector<int> trow, uptr, urow;
+  std::vector<unsigned short> lcol;
+  int nblk = 0;
+  bool ok = false;
+};
+
+TileSet make_tiles(const HostCSR& W, const TileShape& sh) {
+  TileSet T;
   const int n = W.n_rows;
   std::vector<int> trow{0}, stamp(n, -1);
   {
-    int r0 = 0, touched = 0;
+    int r0 = 0, touched = 0, tile = 0;
     int64_t ents = 0;
-    auto add_row = [&](int r, int tile, bool count_only, int& cnt) {
-      int c = 0;
-      if (stamp[r] != tile) ++c;
+    auto count_new = [&](int r) {  // distinct rows row r adds to the current tile
+      int c = stamp[r] != tile ? 1 : 0;
       for (int64_t q = W.ptr[r]; q < W.ptr[r + 1]; ++q)
         if (stamp[W.col[q]] != tile) ++c;
-      if (count_only) {
-        // distinct new rows of this row alone (its columns are distinct)
-        cnt = c;
-        return;
-      }
-      stamp[r] = tile;
-      for (int64_t q = W.ptr[r]; q < W.ptr[r + 1]; ++q) stamp[W.col[q]] = tile;
-      cnt = c;
+      return c;
     };
-    int tile = 0;
     for (int r = 0; r < n; ++r) {
-      int c = 0;
-      add_row(r, tile, true, c);
+      int c = count_new(r);
       const int64_t e = W.ptr[r + 1] - W.ptr[r];
-      if (r > r0 && (r - r0 >= kTileRows || touched + c > kTileCols || ents + e > kTileNnz)) {
+      if (r > r0 && (r - r0 >= sh.rows || touched + c > sh.cols || ents + e > sh.nnz)) {
         trow.push_back(r);
         ++tile;
         r0 = r;
         touched = 0;
         ents = 0;
-        add_row(r, tile, true, c);
+        c = count_new(r);
       }
-      if (c > kTileCols || e > kTileNnz) return;  // one row alone exceeds a cap
-      add_row(r, tile, false, c);
+      if (c > sh.cols || e > sh.nnz) return T;  // one row alone exceeds a cap
+      stamp[r] = tile;
+      for (int64_t q = W.ptr[r]; q < W.ptr[r + 1]; ++q) stamp[W.col[q]] = tile;
       touched += c;
       ents += e;
     }
@@ -1054,28 +1052,97 @@ void build_tiles(const HostCSR& W, LevelDev& D, hipStream_t s) {
   std::vector<int> uptr(nblk + 1, 0), urow;
   for (int t = 0; t < nblk; ++t) {
     // the grouping above guarantees the caps; a block that broke one would
-    // overrun the kernel's LDS arrays, so the level would stay untiled
-    if (static_cast<int>(urows[t].size()) > kTileCols ||
-        W.ptr[trow[t + 1]] - W.ptr[trow[t]] > kTileNnz || trow[t + 1] - trow[t] > kTileRows)
-      return;
+    // overrun the kernel's LDS arrays, so the shape would not be used
+    if (static_cast<int>(urows[t].size()) > sh.cols ||
+        W.ptr[trow[t + 1]] - W.ptr[trow[t]] > sh.nnz || trow[t + 1] - trow[t] > sh.rows)
+      return T;
     uptr[t + 1] = uptr[t] + static_cast<int>(urows[t].size());
   }
   urow.reserve(uptr[nblk]);
   for (auto& u : urows) urow.insert(urow.end(), u.begin(), u.end());
-  D.t_row.upload(trow, s);
-  D.t_uptr.upload(uptr, s);
-  D.t_urow.upload(urow, s);
-  D.t_lcol.upload(lcol, s);
+  T.trow = std::move(trow);
+  T.uptr = std::move(uptr);
+  T.urow = std::move(urow);
+  T.lcol = std::move(lcol);
+  T.nblk = nblk;
+  T.ok = true;
+  return T;
+}
+
+void install_tiles(const TileSet& T, int kind, LevelDev& D, hipStream_t s) {
+  D.t_row.upload(T.trow, s);
+  D.t_uptr.upload(T.uptr, s);
+  D.t_urow.upload(T.urow, s);
+  D.t_lcol.upload(T.lcol, s);
+  D.A.t_kind = kind;
   D.A.t_row = D.t_row.p;
   D.A.t_uptr = D.t_uptr.p;
   D.A.t_urow = D.t_urow.p;
   D.A.t_lcol = D.t_lcol.p;
-  D.A.t_nblk = nblk;
+  D.A.t_nblk = T.nblk;
   MMD_HIP(hipStreamSynchronize(s));  // the host lists must outlive their copies
+}
+
+// Build-time autotuning of the tile shape: every shape whose tiling exists is
+// installed in turn and timed with HIP events on the fused block-CG step at
+// 256 columns (one warm-up and three timed launches on zero data; the
+// kernels' time does not depend on the values), and the fastest is kept.
+// MMDEIG_TILE=<k> forces shape k.
+void build_tiles(const HostCSR& W, LevelDev& D, hipStream_t s) {
+  const int n = W.n_rows;
+  int forced = -1;
+  if (const char* e = std::getenv("MMDEIG_TILE")) {
+    if (e[0]) forced = std::atoi(e);
+  }
+  std::vector<TileSet> sets(kNumTileShapes);
+  std::vector<int> cand;
+  for (int k = 0; k < kNumTileShapes; ++k) {
+    if (forced >= 0 && k != forced) continue;
+    sets[k] = make_tiles(W, kTileShapes[k]);
+    if (sets[k].ok) cand.push_back(k);
+  }
+  if (cand.empty()) return;
+  std::vector<double> us(kNumTileShapes, -1.0);
+  int best = cand[0];
+  if (cand.size() > 1) {
+    const int b = 256;
+    DBuf<double> X((size_t)n * b), Y((size_t)n * b), P((size_t)n * b), beta(b),
+        part((size_t)kRedBlocks * b);
+    MMD_HIP(hipMemsetAsync(X.p, 0, sizeof(double) * (size_t)n * b, s));
+    MMD_HIP(hipMemsetAsync(Y.p, 0, sizeof(double) * (size_t)n * b, s));
+    MMD_HIP(hipMemsetAsync(P.p, 0, sizeof(double) * (size_t)n * b, s));
+    MMD_HIP(hipMemsetAsync(beta.p, 0, sizeof(double) * b, s));
+    hipEvent_t e0, e1;
+    MMD_HIP(hipEventCreate(&e0));
+    MMD_HIP(hipEventCreate(&e1));
+    for (int k : cand) {
+      install_tiles(sets[k], k, D, s);
+      spmm(D.A, X.p, b, Y.p, b, b, s, true, false, beta.p, P.p, b, part.p);
+      MMD_HIP(hipEventRecord(e0, s));
+      for (int r = 0; r < 3; ++r) spmm(D.A, X.p, b, Y.p, b, b, s, true, false, beta.p, P.p, b, part.p);
+      MMD_HIP(hipEventRecord(e1, s));
+      MMD_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      MMD_HIP(hipEventElapsedTime(&ms, e0, e1));
+      us[k] = 1000.0 * ms / 3.0;
+    }
+    best = cand[0];
+    for (int k : cand)
+      if (us[k] < us[best]) best = k;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  install_tiles(sets[best], best, D, s);
   const char* e = std::getenv("MMDEIG_LOG");
-  if (e && std::atoi(e) != 0)
-    std::fprintf(stderr, "[mmd_build] level-0 tiles: %d blocks, %.1f rows and %.1f columns per block on average\n",
-                 nblk, static_cast<double>(n) / nblk, static_cast<double>(uptr[nblk]) / nblk);
+  if (e && std::atoi(e) != 0) {
+    std::fprintf(stderr, "[mmd_build] level-0 tile shapes (rows x staged rows, us per 256-column step):");
+    for (int k = 0; k < kNumTileShapes; ++k)
+      if (us[k] >= 0) std::fprintf(stderr, " %dx%d %.1f", kTileShapes[k].rows, kTileShapes[k].cols, us[k]);
+    const TileSet& T = sets[best];
+    std::fprintf(stderr, "; using %dx%d: %d blocks, %.1f rows and %.1f staged rows per block\n",
+                 kTileShapes[best].rows, kTileShapes[best].cols, T.nblk,
+                 static_cast<double>(n) / T.nblk, static_cast<double>(T.uptr[T.nblk]) / T.nblk);
+  }
 }
 
 void upload_hierarchy(mmd_handle& h, hipStream_t s) {

@@ -466,6 +466,7 @@ void Solver::ensure32() {
   D.A32.col = A.col;
   D.A32.val = D.a_val32.p;
   D.A32.diag = A.diag ? D.a_diag32.p : nullptr;
+  D.A32.t_kind = A.t_kind;
   D.A32.t_row = A.t_row;
   D.A32.t_uptr = A.t_uptr;
   D.A32.t_urow = A.t_urow;

@@ -422,6 +422,44 @@ def test_fp32_level0_operator_elementwise(built, torch_cuda, b):
     assert np.abs(Y - Y64).max() > 0
 
 
+@pytest.mark.parametrize("shape", [0, 1, 2])
+def test_level0_tile_shapes(torch_cuda, shape, monkeypatch):
+    """Every tile shape of the LDS-staged level-0 SpMMs, forced instead of
+    chosen by the build-time timing (MMDEIG_TILE): the FP64 product (plain
+    and inside the fused block CG of a solve) and the FP32 product of the
+    edge form, with ragged column slices."""
+    from paper_1804_03415_amd import Decomposition
+    torch = torch_cuda
+    monkeypatch.setenv("MMDEIG_TILE", str(shape))
+    p = wl.rgg(6000, 7)
+    dec = Decomposition.from_problem(p, levels=1)
+    E = krylov.EdgeForm(p.scipy())
+    for b in (33, 70, 257):
+        X = wl.random_block(p.n, b, seed=90 + b)
+        ref = E @ X
+        Y = dec.apply(0, "A", _t(torch, X)).cpu().numpy()
+        assert np.abs(Y - ref).max() <= 1e-12 * np.abs(ref).max()
+    rhs = wl.random_block(p.n, 70, seed=97)
+    Xs, it = dec.solve(0, 0, _t(torch, rhs), tol=1e-10)
+    Xs = Xs.cpu().numpy()
+    res = np.linalg.norm(rhs - p.scipy() @ Xs, axis=0) / np.linalg.norm(rhs, axis=0)
+    assert np.all(res <= 1.5e-10 + solve_floor(p.scipy(), Xs, rhs))
+    E32 = krylov.EdgeForm(p.scipy())
+    E32.w = E32.w.astype(np.float32).astype(np.float64)
+    E32.s = E32.s.astype(np.float32).astype(np.float64)
+    for b in (70, 129):
+        X = wl.random_block(p.n, b, seed=80 + b).astype(np.float32).astype(np.float64)
+        ref = E32 @ X
+        ax = np.abs(X)
+        mag = E32.s[:, None] * ax + np.stack(
+            [np.bincount(E32.rows, weights=E32.w * (ax[E32.rows, c] + ax[E32.cols, c]),
+                         minlength=p.n) for c in range(b)], axis=1)
+        deg = np.bincount(E32.rows, minlength=p.n)
+        Y = dec.apply(0, "A32", _t(torch, X)).cpu().numpy()
+        assert np.all(np.abs(Y - ref) <= (deg + 3)[:, None] * 2.0 ** -24 * mag + 1e-300)
+    dec.close()
+
+
 # ------------------------------------------------------------------- sign rule, element-wise
 @pytest.mark.parametrize("case", ["rgg", "knn"])
 def test_eigenvectors_elementwise_after_sign_rule(torch_cuda, case):
