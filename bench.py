@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--mixed-steps", type=int, default=1,
                     help="timed eigensolves of the FP32-CG + FP64-refinement form after the "
                          "main run (0: skip), compared pair by pair with the main run")
+    ap.add_argument("--solve-stream", default="side", choices=["side", "default"],
+                    help="run the eigensolves on a stream of their own (block-CG chunks "
+                         "replayed as HIP graphs) or on torch's default stream (no graphs)")
     ap.add_argument("--k0-steps", type=int, default=1,
                     help="timed eigensolves of restarted Lanczos on A^-1 without the "
                          "hierarchy (levels = 0: IRLM with CG solves, the paper's comparison "
@@ -111,6 +114,21 @@ def per_pair_angles(lam, V, W, gap=1e-6):
 
 
 def timed_solves(dec, a, precision, steps, warmup):
+    """Warm-up and timed eigensolves on a stream of their own (not the legacy
+    default stream), so the library can replay fixed CG chunks as HIP graphs;
+    --solve-stream default runs them on torch's default stream instead."""
+    import contextlib
+    import torch
+    ctx = contextlib.nullcontext()
+    if getattr(a, "solve_stream", "side") == "side":
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        ctx = torch.cuda.stream(side)
+    with ctx:
+        return _timed_solves(dec, a, precision, steps, warmup)
+
+
+def _timed_solves(dec, a, precision, steps, warmup):
     import torch
     for w in range(warmup):
         _, _, st = dec.eig_leftmost(a.nev, tol=a.tol, precision=precision, alpha=a.alpha,

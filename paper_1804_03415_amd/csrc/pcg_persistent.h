@@ -35,12 +35,15 @@ struct Pcg1Plan {
   DBuf<int> part;  // grid + 1 row boundaries
 };
 // grid_cap: preferred block count (more are taken when the slices need the
-// LDS of more blocks).
-void pcg1_plan(const CsrView& A, const std::vector<int>& rp, Pcg1Plan& plan, int grid_cap = 112);
+// LDS of more blocks).  The block partition is copied on stream s (ordered
+// with the solver's work; no legacy-stream copy, so another thread may be
+// capturing a graph meanwhile) and s is synchronised.
+void pcg1_plan(const CsrView& A, const std::vector<int>& rp, Pcg1Plan& plan, hipStream_t s,
+               int grid_cap = 112);
 // Plan for the resident flexible PCG on (A, M) (host row pointers rpa, rpm):
 // the fewest blocks (multiple of 8, at least 16) whose slices fit in LDS.
 void pcg1_plan_flex(const CsrView& A, const std::vector<int>& rpa, const CsrView& M,
-                    const std::vector<int>& rpm, Pcg1Plan& plan);
+                    const std::vector<int>& rpm, Pcg1Plan& plan, hipStream_t s);
 
 // Launch on stream s (asynchronous).  Stop rule ||r|| <= tol ||b||; the inner
 // CG stops at ||r_in|| <= tol_in ||r||.  Plain CG (no M) runs the resident

@@ -880,7 +880,8 @@ void pcg1(Pcg1Args a, hipStream_t s, const Pcg1Plan* plan) {
                                      dim3(kThreads), args, 0, s));
 }
 
-void pcg1_plan(const CsrView& A, const std::vector<int>& rp, Pcg1Plan& plan, int grid_cap) {
+void pcg1_plan(const CsrView& A, const std::vector<int>& rp, Pcg1Plan& plan, hipStream_t s,
+               int grid_cap) {
   plan.resident = false;
   const int n = A.n_rows;
   if (n == 0 || (int)rp.size() != n + 1) return;
@@ -939,14 +940,16 @@ void pcg1_plan(const CsrView& A, const std::vector<int>& rp, Pcg1Plan& plan, int
   MMD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cg1_res, kThreads, lds));
   if (per <= 0 || grid > per * cus) return;
   plan.part.ensure(grid + 1);
-  MMD_HIP(hipMemcpy(plan.part.p, part.data(), sizeof(int) * (grid + 1), hipMemcpyHostToDevice));
+  MMD_HIP(hipMemcpyAsync(plan.part.p, part.data(), sizeof(int) * (grid + 1),
+                         hipMemcpyHostToDevice, s));
+  MMD_HIP(hipStreamSynchronize(s));  // part (host) must outlive the copy
   plan.grid = grid;
   plan.lds = lds;
   plan.resident = true;
 }
 
 void pcg1_plan_flex(const CsrView& A, const std::vector<int>& rpa, const CsrView& M,
-                    const std::vector<int>& rpm, Pcg1Plan& plan) {
+                    const std::vector<int>& rpm, Pcg1Plan& plan, hipStream_t s) {
   plan.resident = false;
   plan.flex = true;
   const int n = A.n_rows;
@@ -996,7 +999,9 @@ void pcg1_plan_flex(const CsrView& A, const std::vector<int>& rpa, const CsrView
   MMD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_pcg1_res, kThreads, lds));
   if (per <= 0 || grid > per * cus) return;
   plan.part.ensure(grid + 1);
-  MMD_HIP(hipMemcpy(plan.part.p, part.data(), sizeof(int) * (grid + 1), hipMemcpyHostToDevice));
+  MMD_HIP(hipMemcpyAsync(plan.part.p, part.data(), sizeof(int) * (grid + 1),
+                         hipMemcpyHostToDevice, s));
+  MMD_HIP(hipStreamSynchronize(s));  // part (host) must outlive the copy
   plan.grid = grid;
   plan.lds = lds;
   plan.resident = true;

@@ -8,6 +8,7 @@
 #include "solver.h"
 
 #include <algorithm>
+#include <functional>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -153,6 +154,7 @@ Solver::Solver(mmd_handle& h, hipStream_t s, const eig_opts& o, eig_stats* st)
   if (o_.max_refine <= 0) o_.max_refine = 200;
   hd_.ensure(4096);
   hi_.ensure(4096);
+  if (const char* e = std::getenv("MMDEIG_GRAPHS")) graphs_ = !(e[0] == '0' && e[1] == 0);
 }
 
 Solver::~Solver() {
@@ -268,10 +270,12 @@ void Solver::cg(int k, OpKind op, const double* B, int ldb, double* X, int ldx, 
   cg_init(sc, p1, p2, nb, b, tol, parent, s_);
   MMD_HIP(hipMemsetAsync(sc.notspd, 0, sizeof(int), s_));
   int64_t n_wide = 0, n_narrow = 0, col_iters = 0;
+  auto count_steps = [&](int steps) {
+    if (bc > 32) n_wide += steps;
+    else n_narrow += steps;
+    col_iters += static_cast<int64_t>(bc) * steps;
+  };
   auto iterate = [&](bool first) {
-    if (bc > 32) ++n_wide;
-    else ++n_narrow;
-    col_iters += bc;
     int np;
     if (csr) {
       // fused: P = R + beta P, Q = A R + beta Q (= A P), partial p.q per block
@@ -299,6 +303,21 @@ void Solver::cg(int k, OpKind op, const double* B, int ldb, double* X, int ldx, 
     for (int t = 0; t < fixed_iters; ++t) iterate(t == 0);
     return;
   }
+  // A chunk of steps on an unchanged working set is the same kernel sequence
+  // with the same arguments every time, so after the first chunk it is
+  // captured once per working set (stage) as a HIP graph and replayed.  The level-0 wide
+  // steps are not captured: their SpMM launches carry the library's own
+  // event timing, and at ~300 us each their launch gaps do not matter.
+  hipGraphExec_t gexec = nullptr;
+  int gstage = -1, gchunk = 0;
+  auto drop_graph = [&]() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+  };
+  struct GraphGuard {
+    std::function<void()> f;
+    ~GraphGuard() { f(); }
+  } graph_guard{drop_graph};
   // the working state moves to a compact copy once a quarter of its columns
   // have converged; converged columns keep their final iterate in X
   int* d_idx = pool_.i(tag + ":cidx", b);
@@ -369,10 +388,36 @@ void Solver::cg(int k, OpKind op, const double* B, int ldb, double* X, int ldx, 
       bc = na;
     }
     const int chunk = bc > 32 ? 8 : 16;
-    for (int t = 0; t < chunk; ++t) {
-      iterate(first);
-      first = false;
+    const bool timed = k == 0 && op == OpKind::A && bc > 32;
+    // the legacy default stream cannot be captured: graphs run on the
+    // caller's (or the batch's) own streams only
+    if (graphs_ && s_ != nullptr && !first && !timed) {
+      if (!gexec || gstage != stage || gchunk != chunk) {
+        drop_graph();
+        MMD_HIP(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
+        hipGraph_t g = nullptr;
+        try {
+          for (int t = 0; t < chunk; ++t) iterate(false);
+        } catch (...) {
+          (void)hipStreamEndCapture(s_, &g);
+          if (g) (void)hipGraphDestroy(g);
+          throw;
+        }
+        MMD_HIP(hipStreamEndCapture(s_, &g));
+        const hipError_t e = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        MMD_REQUIRE(e == hipSuccess, MMD_EHIP, "hipGraphInstantiate failed");
+        gstage = stage;
+        gchunk = chunk;
+      }
+      MMD_HIP(hipGraphLaunch(gexec, s_));
+    } else {
+      for (int t = 0; t < chunk; ++t) {
+        iterate(first);
+        first = false;
+      }
     }
+    count_steps(chunk);
     done += chunk;
   }
   take_iters();
@@ -420,12 +465,12 @@ bool Solver::pcg_single(int k, const double* B, double* X, double tol, bool use_
       sync();
       it = plans_.emplace(k, Pcg1Plan()).first;
       if (k == 0) {
-        pcg1_plan(a.A, rp, it->second, batcher_ ? 32 : 112);
+        pcg1_plan(a.A, rp, it->second, s_, batcher_ ? 32 : 112);
       } else {
         std::vector<int> rpm(n + 1);
         d2h(rpm.data(), a.M.rowptr, n + 1);
         sync();
-        pcg1_plan_flex(a.A, rp, a.M, rpm, it->second);
+        pcg1_plan_flex(a.A, rp, a.M, rpm, it->second, s_);
       }
     }
     plan = &it->second;

@@ -460,6 +460,39 @@ def test_level0_tile_shapes(torch_cuda, shape, monkeypatch):
     dec.close()
 
 
+def test_graph_replay_matches_eager(torch_cuda, monkeypatch):
+    """Block-CG chunks replayed as HIP graphs run the same kernels with the
+    same arguments as the eager launches: a narrow level-0 block solve, the CG
+    on B^(1) and a whole eigensolve give bit-identical results with graphs on and
+    off, over many replays (each chunk of a stage replays one graph, with the
+    host's convergence checks and compactions between the replays)."""
+    from paper_1804_03415_amd import Decomposition
+    torch = torch_cuda
+    p = wl.rgg(3000, 5)
+    dec = Decomposition.from_problem(p, levels=2)
+    info = dec.info()
+    out = {}
+    side = torch.cuda.Stream()   # graphs are captured on non-default streams only
+    for g in ("0", "1"):
+        monkeypatch.setenv("MMDEIG_GRAPHS", g)
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            r1 = wl.random_block(info["sizes"][0], 4, seed=11)
+            X1, it1 = dec.solve(0, 0, _t(torch, r1), tol=1e-10)
+            nb = info["sizes"][0] - info["sizes"][1]
+            rb = wl.random_block(nb, 6, seed=12)
+            XB, itB = dec.solve(0, 1, _t(torch, rb), tol=1e-10)
+            lam, V, st = dec.eig_leftmost(25, tol=1e-10)
+        side.synchronize()
+        out[g] = (X1.cpu().numpy(), it1, XB.cpu().numpy(), itB, lam, V.cpu().numpy())
+    a, b = out["0"], out["1"]
+    assert np.array_equal(a[1], b[1]) and np.array_equal(a[3], b[3])
+    assert max(a[1]) > 32 and max(a[3]) > 32      # several chunks, so several replays
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    dec.close()
+
+
 # ------------------------------------------------------------------- sign rule, element-wise
 @pytest.mark.parametrize("case", ["rgg", "knn"])
 def test_eigenvectors_elementwise_after_sign_rule(torch_cuda, case):
