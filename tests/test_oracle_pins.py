@@ -570,6 +570,33 @@ def test_shift_cluster_reference():
 
 
 # --------------------------------------------------------------------------- prescribed-accuracy partition
+def test_split_energy_sums_below_the_matrix():
+    """Section 2.2 patch bound: the split energies of any partition sum to at
+    most the level matrix (A - sum_P E_P is positive semidefinite), also for a
+    dense coarse Galerkin matrix with positive off-diagonals; on a Laplacian
+    plus a nonnegative diagonal they equal the interior energies."""
+    p = wl.rgg(600, 4)
+    A0 = p.scipy()
+    M = mm.build_mmd(A0, coords=p.coords, levels=1, exact_max_n=10 ** 6)
+    A1 = M.levels[1].A.tocsr()
+    assert (A1 - sp.diags(A1.diagonal())).max() > 0      # not an M-matrix
+    rng = np.random.default_rng(3)
+    for A in (A0, A1):
+        n = A.shape[0]
+        perm = rng.permutation(n)
+        cuts = np.sort(rng.choice(np.arange(1, n), size=n // 5, replace=False))
+        patches = [np.sort(c) for c in np.split(perm, cuts)]
+        S = np.zeros((n, n))
+        for mem in patches:
+            S[np.ix_(mem, mem)] += energy.split_energy(A, mem)
+        w = np.linalg.eigvalsh(A.toarray() - S)
+        assert w.min() >= -1e-12 * abs(A).max()
+    for mem in [np.sort(rng.choice(600, 7, replace=False)) for _ in range(20)]:
+        assert np.allclose(energy.split_energy(A0, mem), energy.interior_energy(A0, mem),
+                           rtol=0, atol=1e-14 * abs(A0).max())
+
+
+
 def test_eps_partition_meets_its_bounds():
     """SwissRoll graph (Section 7.1, a 1500-point sample at the full roll's
     point density) partitioned to prescribed accuracy with the paper's
