@@ -72,6 +72,21 @@ int spmm(const CsrView& A, const double* X, int ldx, double* Y, int ldy, int b,
          double* P = nullptr, int ldp = 0, double* partial = nullptr,
          const double* dot_with = nullptr, int ld_dot = 0);
 
+// One level-0 block-CG step with the previous step's update folded in
+// (tiled edge form only: cg_tile_ok).  pend: X += alpha P and
+// r = Ri - alpha Qi (alpha per column, the previous step's), written to Ro;
+// then P = r + beta P, Qo = A r + beta Qi (first: P = r, Qo = A r).  A pending
+// step needs Ro != Ri and Qo != Qi (other workgroups still gather the old
+// rows); without pend Ro is unused and Qo may equal Qi.  Ri, Qi, Ro, Qo, P
+// share the leading dimension ld.  partial receives four n_blk x b blocks,
+// pstride (>= kRedBlocks * b) apart: p.q, r.q, q.q, r.r of the new vectors.
+// Returns n_blk.
+bool cg_tile_ok(const CsrView& A);
+int cg_tile_step(const CsrView& A, double* X, int ldx, const double* Ri, const double* Qi,
+                 double* Ro, double* Qo, double* P, int ld, int b, bool pend, bool first,
+                 const double* alpha, const double* beta, double* partial, size_t pstride,
+                 hipStream_t s);
+
 // ---------------------------------------------------------------- Householder
 // y_red = U^T x  (x: nfine x b, y: nred x b)
 void house_ut(const HouseView& H, const double* x, int ldx, double* y, int ldy, int b,
@@ -119,6 +134,14 @@ void cg_beta_flag(ColScalars sc, const double* part_rr, int nblk, int b, int* up
 // tol2 = delta2, alpha = 0, active = 1, upd = 0
 void reliable_scalars(ColScalars sc, const double* rr_true, double delta2, double restart2,
                       int b, int* upd, hipStream_t s);
+// deferred-update step scalars (after cg_tile_step): alpha = r.r / p.q left
+// pending, the next r.r from r.r - 2 alpha r.q + alpha^2 q.q for the stop test
+// and beta; a column whose new r.r meets the tolerance stops with alpha = 0
+void cg_defer_scalars(ColScalars sc, const double* part, size_t pstride, int nblk, int b,
+                      hipStream_t s);
+// after cg_update applied the pending alphas: alpha = 0; active columns take
+// the direct r.r (part_rr), rescale beta to it and stop at the tolerance
+void cg_defer_flush(ColScalars sc, const double* part_rr, int nblk, int b, hipStream_t s);
 // flexible PCG stop test on ||r||^2 (part_rr); marks converged columns inactive
 void pcg_conv(ColScalars sc, const double* part_rr, int nblk, int b, hipStream_t s);
 // flexible PCG beta = (r.z - r.zold) / rz ; rz = r.z

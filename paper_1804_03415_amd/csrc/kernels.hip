@@ -465,6 +465,208 @@ int launch_spmm_tile(const CsrView& A, const double* X, int ldx, double* Y, int 
   return gx;
 }
 
+// One block-CG step on the tiled level-0 edge form with the previous step's
+// iterate and residual update folded in.  With a pending step length
+// a = alpha[c] (PEND), every own row does
+//   x += a p ;  r -= a q ;  p = r + beta p ;  q = A r + beta q
+// and the gathered rows of r are formed as r - a q while they are staged, so
+// the update needs no pass over the block of its own (one pass fewer over R,
+// P and Q per step than the fused SpMM followed by k_cg_update).  Own rows of
+// Q come from the row loads that the q update needs anyway; only the halo
+// rows load Q a second time.  Other workgroups stage these rows of R and Q
+// as halo while this one updates them, so a pending step reads Ri, Qi and
+// writes the new r, q to Ro, Qo (separate buffers, swapped by the caller
+// every step); P and X are read and written only by the row's owner.  A
+// step without PEND writes no r and may take Qo == Qi: the halo entries of
+// Qi it loads are never used.  Four partial sums per block and column, of the
+// new vectors: p.q, r.q, q.q and r.r (k_cg_defer_scalars turns them into
+// alpha and, through |r - alpha q|^2 = r.r - 2 alpha r.q + alpha^2 q.q, the
+// next beta).  Without PEND (first step, or the step after a flush) r is
+// staged as stored and x, r are neither read nor written.  Tiling, staging
+// order and XCD mapping as in k_spmm_tile.
+template <bool PEND, int KIND>
+__global__ __launch_bounds__(kBlock, kTileShapes[KIND].wgs_per_cu) void k_cg_tile(
+    const int* __restrict__ rowptr, const double* __restrict__ val,
+    const double* __restrict__ diag, const int* __restrict__ trow,
+    const int* __restrict__ uptr, const int* __restrict__ urow,
+    const unsigned short* __restrict__ lcol, int nblk, double* __restrict__ X, int ldx,
+    const double* __restrict__ Ri, const double* Qi, double* __restrict__ Ro, double* Qo,
+    double* __restrict__ P, int ld, int b,
+    int first_arg, const double* __restrict__ alpha, const double* __restrict__ beta,
+    double* __restrict__ partial, size_t pstride) {
+  constexpr int WPB = kBlock / kWave;
+  constexpr int kTileRows = kTileShapes[KIND].rows;
+  constexpr int kTileCols = kTileShapes[KIND].cols;
+  constexpr int kTileNnz = kTileShapes[KIND].nnz;
+  constexpr int RPW = kTileRows / WPB;
+  constexpr int SPW = kTileCols / WPB;
+  __shared__ double sx[kTileCols * kWave];  // also the partial-sum buffer at the end
+  __shared__ double sv[kTileNnz];
+  __shared__ unsigned short sc[kTileNnz];
+  __shared__ int sp[kTileRows + 1];
+  static_assert(kTileCols >= 4 * WPB, "the four reductions reuse the staging buffer");
+  static_assert(kBlock == 4 * kWave, "one wavefront per partial sum in the reduction");
+  const bool first = !PEND && first_arg != 0;  // a pending step is never the first
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int cc = blockIdx.y * kWave + lane;
+  const bool cok = cc < b;
+  const int cx = cok ? cc : 0;  // lanes past b read column 0 and store nothing
+  const double bt = (cok && !first) ? beta[cc] : 0.0;
+  const double al = (PEND && cok) ? alpha[cc] : 0.0;
+  double s_pq = 0.0, s_rq = 0.0, s_qq = 0.0, s_rr = 0.0;
+  const int nx = (gridDim.x % 8 == 0) ? 8 : 1;
+  const int bpx = gridDim.x / nx;
+  const int xcd = blockIdx.x % nx, bl = blockIdx.x / nx;
+  const int tpx = (nblk + nx - 1) / nx;
+  const int thi = min(nblk, (xcd + 1) * tpx);
+  for (int t = xcd * tpx + bl; t < thi; t += bpx) {
+    const int r0 = trow[t];
+    const int r1 = trow[t + 1];
+    const int nr = r1 - r0;
+    const int u0 = uptr[t], nu = uptr[t + 1] - u0;
+    const int e0 = rowptr[r0], ne = rowptr[r1] - e0;
+    // w[q] = old q (= A p) of the row in slot wid + WPB q.  The slots below
+    // nr are the own rows in order, so w[k] (k < RPW) is also the old q of own
+    // row r0 + wid + k WPB, kept for the q update; the other entries serve
+    // the residual update of the halo rows (PEND only).
+    double w[SPW];
+    {
+      constexpr int EPT = kTileNnz / kBlock;
+      double ev[EPT];
+      unsigned short ec[EPT];
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const int e = threadIdx.x + q * kBlock;
+        ev[q] = e < ne ? val[e0 + e] : 0.0;
+        ec[q] = e < ne ? lcol[e0 + e] : 0;
+      }
+      const int rp = threadIdx.x <= nr ? rowptr[r0 + threadIdx.x] - e0 : 0;
+      // slot wid + WPB q of the tile is held by lane q of this wavefront
+      const int myu = wid + WPB * lane;
+      const int ridx = (lane < SPW && myu < nu) ? urow[u0 + myu] : -1;
+      double v[SPW];
+#pragma unroll
+      for (int q = 0; q < SPW; ++q) {
+        const int j = __builtin_amdgcn_readlane(ridx, q);
+        v[q] = j >= 0 ? Ri[(size_t)j * ld + cx] : 0.0;
+        w[q] = ((PEND || (!first && q < RPW)) && j >= 0) ? Qi[(size_t)j * ld + cx] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const int e = threadIdx.x + q * kBlock;
+        if (e < ne) {
+          sv[e] = ev[q];
+          sc[e] = ec[q];
+        }
+      }
+      if (threadIdx.x <= nr) sp[threadIdx.x] = rp;
+#pragma unroll
+      for (int q = 0; q < SPW; ++q) {
+        const int u = wid + WPB * q;
+        if (u < nu) sx[u * kWave + lane] = PEND ? v[q] - al * w[q] : v[q];
+      }
+    }
+    __syncthreads();
+    double po[RPW];
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) {
+      const int i = r0 + wid + k * WPB;
+      const size_t ri = (size_t)(i < r1 ? i : r0);
+      po[k] = (!first && i < r1) ? __builtin_nontemporal_load(P + ri * ld + cx) : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) {
+      const int i = r0 + wid + k * WPB;
+      if (i < r1) {
+        const int l = i - r0;
+        // the iterate's row: loaded here so that its latency overlaps the
+        // row's gathers rather than holding registers across the tile
+        const double xo = (PEND && cok) ? __builtin_nontemporal_load(X + (size_t)i * ldx + cc) : 0.0;
+        const double xi = sx[l * kWave + lane];
+        const int lo = sp[l], hi = sp[l + 1];
+        double a0 = 0.0;
+        for (int base = 0; base < hi - lo; base += kWave) {
+          const int m = min(kWave, hi - lo - base);
+          const int jv = lane < m ? static_cast<int>(sc[lo + base + lane]) : 0;
+          const double wv = lane < m ? sv[lo + base + lane] : 0.0;
+          for (int k0 = 0; k0 < m; k0 += 8) {
+            double xs[8], ws[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const int j = __builtin_amdgcn_readlane(jv, k0 + q);
+              ws[q] = readlane_d(wv, k0 + q);
+              xs[q] = sx[j * kWave + lane];
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) a0 += ws[q] * (xi - xs[q]);
+          }
+        }
+        const double y = diag[i] * xi + a0 + bt * w[k];
+        const double pn = xi + bt * po[k];
+        if (cok) {
+          const size_t iv = (size_t)i * ld + cc;
+          __builtin_nontemporal_store(pn, P + iv);
+          __builtin_nontemporal_store(y, Qo + iv);
+          if (PEND) {
+            __builtin_nontemporal_store(xi, Ro + iv);
+            __builtin_nontemporal_store(xo + al * po[k], X + (size_t)i * ldx + cc);
+          }
+          s_pq += pn * y;
+          s_rq += xi * y;
+          s_qq += y * y;
+          s_rr += xi * xi;
+        }
+      }
+    }
+    __syncthreads();  // the next tile overwrites the staging
+  }
+  double* red = sx;
+  red[(0 * WPB + wid) * kWave + lane] = s_pq;
+  red[(1 * WPB + wid) * kWave + lane] = s_rq;
+  red[(2 * WPB + wid) * kWave + lane] = s_qq;
+  red[(3 * WPB + wid) * kWave + lane] = s_rr;
+  __syncthreads();
+  {
+    const int m = wid;  // wavefront m sums partial m
+    double s = 0.0;
+    for (int w = 0; w < WPB; ++w) s += red[(m * WPB + w) * kWave + lane];
+    if (cok) partial[(size_t)m * pstride + (size_t)blockIdx.x * b + cc] = s;
+  }
+}
+
+template <int KIND>
+void launch_cg_tile_kind(const CsrView& A, double* X, int ldx, const double* Ri, const double* Qi,
+                         double* Ro, double* Qo, double* P, int ld, int b, bool pend,
+                         bool first, const double* alpha,
+                         const double* beta, double* partial, size_t pstride, dim3 grid,
+                         hipStream_t s) {
+  if (pend)
+    hipLaunchKernelGGL((k_cg_tile<true, KIND>), grid, dim3(kBlock), 0, s, A.rowptr, A.val,
+                       A.diag, A.t_row, A.t_uptr, A.t_urow, A.t_lcol, A.t_nblk, X, ldx, Ri, Qi, Ro,
+                       Qo, P, ld, b, 0, alpha, beta, partial, pstride);
+  else
+    hipLaunchKernelGGL((k_cg_tile<false, KIND>), grid, dim3(kBlock), 0, s, A.rowptr, A.val,
+                       A.diag, A.t_row, A.t_uptr, A.t_urow, A.t_lcol, A.t_nblk, X, ldx, Ri, Qi, Ro,
+                       Qo, P, ld, b, first ? 1 : 0, alpha, beta, partial, pstride);
+}
+
+int launch_cg_tile(const CsrView& A, double* X, int ldx, const double* Ri, const double* Qi,
+                   double* Ro, double* Qo, double* P, int ld, int b, bool pend, bool first,
+                   const double* alpha,
+                   const double* beta, double* partial, size_t pstride, hipStream_t s) {
+  int gx = std::min(A.t_nblk, kRedBlocks);
+  if (gx >= 8) gx = gx / 8 * 8;  // whole XCD rounds
+  dim3 grid(gx, ceil_div(b, kWave));
+  switch (A.t_kind) {
+    case 0: launch_cg_tile_kind<0>(A, X, ldx, Ri, Qi, Ro, Qo, P, ld, b, pend, first, alpha, beta, partial, pstride, grid, s); break;
+    case 1: launch_cg_tile_kind<1>(A, X, ldx, Ri, Qi, Ro, Qo, P, ld, b, pend, first, alpha, beta, partial, pstride, grid, s); break;
+    default: launch_cg_tile_kind<2>(A, X, ldx, Ri, Qi, Ro, Qo, P, ld, b, pend, first, alpha, beta, partial, pstride, grid, s); break;
+  }
+  check_launch();
+  return gx;
+}
+
 template <int U, int STEP>
 int launch_r64_t(const CsrView& A, const double* X, int ldx, double* Y, int ldy, int b,
                  hipStream_t s, bool fuse, bool first, const double* beta, double* P, int ldp,
@@ -765,6 +967,78 @@ __global__ __launch_bounds__(kScThreads) void k_cg_beta(ColScalars sc,
 // CG scalars of the reliable-update mixed solve: as k_cg_beta, but a column
 // whose recursive residual has dropped below tol2 * bn2 keeps iterating and
 // raises upd[c], which asks the host for an FP64 residual replacement.
+// Scalars of a deferred-update step (k_cg_tile): partial sums p.q, r.q, q.q
+// and r.r of the step's new vectors, pstride apart.  A column whose new
+// residual (direct r.r) already meets the tolerance stops with no step
+// pending (alpha = 0).  Otherwise alpha = r.r / p.q is left pending for the
+// next step or flush, and the next residual norm |r - alpha q|^2 is taken
+// from the expansion r.r - 2 alpha r.q + alpha^2 q.q for the stop test and
+// beta.  The expansion cancels when the residual drops by about 1/eps in
+// one step; below 64 eps r.r it is not trusted to stop the column (the next
+// step's direct r.r decides).
+__global__ __launch_bounds__(kScThreads) void k_cg_defer_scalars(ColScalars sc,
+                                                                 const double* __restrict__ part,
+                                                                 size_t pstride, int nblk,
+                                                                 int b) {
+  const bool act = col_active(sc, b);
+  const double pq = col_sum(part, nblk, b, act);
+  const double rq = col_sum(part + pstride, nblk, b, act);
+  const double qq = col_sum(part + 2 * pstride, nblk, b, act);
+  const double rr = col_sum(part + 3 * pstride, nblk, b, act);
+  const int c = sc_col();
+  if (threadIdx.x >= kScCols || c >= b) return;
+  sc.alpha[c] = 0.0;
+  sc.beta[c] = 0.0;
+  if (!act) return;
+  sc.rr[c] = rr;
+  sc.rr2[c] = rr;
+  const double stop2 = sc.tol2[c] * sc.bn2[c];
+  if (rr <= stop2) {
+    sc.active[c] = 0;
+    return;
+  }
+  if (!(pq > 0.0)) {
+    sc.notspd[0] = 1;
+    sc.active[c] = 0;
+    return;
+  }
+  const double a = rr / pq;
+  sc.alpha[c] = a;
+  sc.iters[c] += 1;
+  const double rn = rr - 2.0 * a * rq + a * a * qq;
+  const double rp = rn > 0.0 ? rn : 0.0;
+  sc.rr2[c] = rp;
+  if (rn >= 64.0 * 2.220446049250313e-16 * rr && rn <= stop2) {
+    sc.active[c] = 0;  // alpha stays pending: the next step or flush applies it
+    return;
+  }
+  sc.beta[c] = rp / rr;
+  sc.rr[c] = rp;
+}
+
+// After k_cg_update has applied the pending alphas (partial = new r.r):
+// alpha = 0 everywhere; an active column takes its direct r.r, rescales beta
+// from the expanded norm to it, and stops if it meets the tolerance.
+__global__ __launch_bounds__(kScThreads) void k_cg_defer_flush(ColScalars sc,
+                                                               const double* __restrict__ prr,
+                                                               int nblk, int b) {
+  const bool act = col_active(sc, b);
+  const double rr = col_sum(prr, nblk, b, act);
+  const int c = sc_col();
+  if (threadIdx.x >= kScCols || c >= b) return;
+  sc.alpha[c] = 0.0;
+  if (!act) return;
+  const double old = sc.rr[c];
+  sc.rr2[c] = rr;
+  if (rr <= sc.tol2[c] * sc.bn2[c]) {
+    sc.active[c] = 0;
+    sc.beta[c] = 0.0;
+    return;
+  }
+  if (old > 0.0) sc.beta[c] *= rr / old;
+  sc.rr[c] = rr;
+}
+
 __global__ __launch_bounds__(kScThreads) void k_cg_beta_flag(ColScalars sc,
                                                              const double* __restrict__ prr,
                                                              int nblk, int b,
@@ -1334,6 +1608,35 @@ void cg_alpha(ColScalars sc, const double* part_pq, int nblk, int b, hipStream_t
 
 void cg_beta(ColScalars sc, const double* part_rr, int nblk, int b, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_beta, dim3(sc_grid(b)), dim3(kScThreads), 0, s, sc, part_rr,
+                     nblk, b);
+  check_launch();
+}
+
+bool cg_tile_ok(const CsrView& A) { return A.t_uptr && A.diag && !tile_off(); }
+
+int cg_tile_step(const CsrView& A, double* X, int ldx, const double* Ri, const double* Qi,
+                 double* Ro, double* Qo, double* P, int ld, int b, bool pend, bool first,
+                 const double* alpha, const double* beta, double* partial, size_t pstride,
+                 hipStream_t s) {
+  MMD_REQUIRE(cg_tile_ok(A), MMD_EINVAL, "deferred CG step needs the tiled edge form");
+  MMD_REQUIRE(!(pend && first), MMD_EINVAL, "a first step has no pending update");
+  MMD_REQUIRE(!pend || (Ro != Ri && Qo != Qi), MMD_EINVAL,
+              "a pending step writes r and q to buffers other than the ones it gathers");
+  MMD_REQUIRE(pstride >= (size_t)kRedBlocks * b, MMD_EINVAL, "partial stride too small");
+  if (A.n_rows == 0 || b == 0) return 0;
+  return launch_cg_tile(A, X, ldx, Ri, Qi, Ro, Qo, P, ld, b, pend, first, alpha, beta, partial,
+                        pstride, s);
+}
+
+void cg_defer_scalars(ColScalars sc, const double* part, size_t pstride, int nblk, int b,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_defer_scalars, dim3(sc_grid(b)), dim3(kScThreads), 0, s, sc, part,
+                     pstride, nblk, b);
+  check_launch();
+}
+
+void cg_defer_flush(ColScalars sc, const double* part_rr, int nblk, int b, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_defer_flush, dim3(sc_grid(b)), dim3(kScThreads), 0, s, sc, part_rr,
                      nblk, b);
   check_launch();
 }

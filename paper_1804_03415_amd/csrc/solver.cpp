@@ -155,6 +155,7 @@ Solver::Solver(mmd_handle& h, hipStream_t s, const eig_opts& o, eig_stats* st)
   hd_.ensure(4096);
   hi_.ensure(4096);
   if (const char* e = std::getenv("MMDEIG_GRAPHS")) graphs_ = !(e[0] == '0' && e[1] == 0);
+  if (const char* e = std::getenv("MMDEIG_CG_DEFER")) cg_defer_ = !(e[0] == '0' && e[1] == 0);
 }
 
 Solver::~Solver() {
@@ -303,6 +304,44 @@ void Solver::cg(int k, OpKind op, const double* B, int ldb, double* X, int ldx, 
     for (int t = 0; t < fixed_iters; ++t) iterate(t == 0);
     return;
   }
+  // Level-0 wide steps on the tiled form fold each step's X and R update
+  // into the next step's SpMM (cg_tile_step): the step length stays pending
+  // until that kernel, or a flush (k_cg_update) before the working set is
+  // compacted or the loop ends, applies it.
+  // A pending step reads R, Q and writes the new ones to Ra, Qa (other
+  // workgroups still gather the old rows); the pairs swap after it.
+  const bool defer_ok = csr && k == 0 && op == OpKind::A && cg_defer_ && cg_tile_ok(*csr);
+  double* p4 = defer_ok ? pool_.d(tag + ":p4", (size_t)4 * kRedBlocks * b) : nullptr;
+  double* Ra = defer_ok ? pool_.d(tag + ":Ra", (size_t)n * b) : nullptr;
+  double* Qa = defer_ok ? pool_.d(tag + ":Qa", (size_t)n * b) : nullptr;
+  bool pending = false;
+  auto defer_step = [&](bool first_step) {
+    spmm0_begin();
+    const size_t ps = (size_t)kRedBlocks * bc;
+    const int np = pending
+        ? cg_tile_step(*csr, Xw, ldw, R, Q, Ra, Qa, P, bc, bc, true, false, sc.alpha, sc.beta,
+                       p4, ps, s_)
+        : cg_tile_step(*csr, Xw, ldw, R, Q, R, Q, P, bc, bc, false, first_step, sc.alpha,
+                       sc.beta, p4, ps, s_);
+    if (pending) {
+      std::swap(R, Ra);
+      std::swap(Q, Qa);
+    }
+    // matrix once (weights + columns, row pointers, self-loops); pending: X, R,
+    // P, Q read and written once; else R read, P and Q read (not on a first
+    // step) and written
+    const double nnz = static_cast<double>(csr->nnz);
+    const double vec = pending ? 64.0 : first_step ? 24.0 : 40.0;
+    spmm0_end(12.0 * nnz + 12.0 * n + vec * n * static_cast<double>(bc), bc);
+    cg_defer_scalars(sc, p4, ps, np, bc, s_);
+    pending = true;
+  };
+  auto flush_pending = [&]() {
+    if (!pending) return;
+    const int nu = cg_update(Xw, ldw, R, P, Q, bc, n, bc, sc.alpha, p2, s_);
+    cg_defer_flush(sc, p2, nu, bc, s_);
+    pending = false;
+  };
   // A chunk of steps on an unchanged working set is the same kernel sequence
   // with the same arguments every time, so after the first chunk it is
   // captured once per working set (stage) as a HIP graph and replayed.  The level-0 wide
@@ -357,6 +396,7 @@ void Solver::cg(int k, OpKind op, const double* B, int ldb, double* X, int ldx, 
     MMD_REQUIRE(done < maxit, MMD_ENOCONV, "CG reached the iteration cap");
     const int na = static_cast<int>(keep.size());
     if (bc >= 16 && 8 * na <= 7 * bc) {
+      flush_pending();
       take_iters();
       flush_x();
       ++stage;
@@ -383,12 +423,18 @@ void Solver::cg(int k, OpKind op, const double* B, int ldb, double* X, int ldx, 
       P = P2;
       Q = Q2;
       Xw = X2;
+      if (defer_ok) {  // spare pair of this stage: never the source of the next gather
+        Ra = pool_.d(st + "Ra", (size_t)n * na);
+        Qa = pool_.d(st + "Qa", (size_t)n * na);
+      }
       ldw = na;
       sc = sc2;
       bc = na;
     }
     const int chunk = bc > 32 ? 8 : 16;
     const bool timed = k == 0 && op == OpKind::A && bc > 32;
+    const bool defer = defer_ok && timed;
+    if (!defer) flush_pending();
     // the legacy default stream cannot be captured: graphs run on the
     // caller's (or the batch's) own streams only
     if (graphs_ && s_ != nullptr && !first && !timed) {
@@ -411,6 +457,11 @@ void Solver::cg(int k, OpKind op, const double* B, int ldb, double* X, int ldx, 
         gchunk = chunk;
       }
       MMD_HIP(hipGraphLaunch(gexec, s_));
+    } else if (defer) {
+      for (int t = 0; t < chunk; ++t) {
+        defer_step(first);
+        first = false;
+      }
     } else {
       for (int t = 0; t < chunk; ++t) {
         iterate(first);
@@ -420,6 +471,7 @@ void Solver::cg(int k, OpKind op, const double* B, int ldb, double* X, int ldx, 
     count_steps(chunk);
     done += chunk;
   }
+  flush_pending();
   take_iters();
   flush_x();
   if (log_on() && k == 0 && op == OpKind::A && b > 32) {

@@ -151,6 +151,7 @@ class Solver {
   int inner_iters_ = 16;
   bool use_persistent_ = true;
   bool graphs_ = true;             // replay fixed CG chunks as HIP graphs (MMDEIG_GRAPHS=0: off)
+  bool cg_defer_ = true;           // fold the level-0 CG update into the next step (MMDEIG_CG_DEFER=0: off)
   OpBatcher* batcher_ = nullptr;
   std::map<int, Pcg1Plan> plans_;  // resident plain-CG plan per level (level 0)
   double norm_a0_ = 0.0;           // ||A||_inf of level 0 (mixed-precision floor test)

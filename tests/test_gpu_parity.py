@@ -206,6 +206,49 @@ def test_level0_wide_apply_and_solve(built, torch_cuda, b):
     assert np.all(res <= 1.5 * tol + floor)
 
 
+def test_deferred_cg_step_matches_separate_update(torch_cuda, monkeypatch):
+    """Level-0 block CG with each step's X and R update folded into the next
+    step's tiled SpMM (the default) against the form with a separate update
+    pass (MMDEIG_CG_DEFER=0).  The two are the same CG in exact arithmetic;
+    in rounding they differ in the order of the dot products and in beta,
+    whose residual norm is expanded from r.r, r.q and q.q of the previous
+    step instead of summed after the update.  Over hundreds of steps at
+    condition ~1e7 that moves a column's stopping step by a few (a float64
+    model of both forms on a 5000-point RGG: 0 to 2 of ~600), so the
+    comparison is of the work (total column-steps within 1%, each column
+    within 5% + 2 steps) and of the result (both meet the tolerance).  The
+    right-hand sides A^m g (m = 0, 1, 2) converge at different steps, so the
+    working set is compacted several times while steps are pending; 150
+    columns leave a ragged third 64-column slice."""
+    torch = torch_cuda
+    from paper_1804_03415_amd import Decomposition
+    p = wl.rgg(20000, 3)
+    Ad = p.scipy()
+    dec = Decomposition.from_problem(p, levels=2, targets=(4, 8))
+    b = 150
+    g = wl.random_block(p.n, b, seed=77)
+    rhs = g.copy()
+    rhs[:, 50:100] = Ad @ g[:, 50:100]
+    rhs[:, 100:] = Ad @ (Ad @ g[:, 100:])
+    tol = 1e-9
+    out = {}
+    for mode in ("1", "0"):
+        monkeypatch.setenv("MMDEIG_CG_DEFER", mode)
+        X, it = dec.solve(0, 0, _t(torch, rhs), tol=tol)
+        out[mode] = (X.cpu().numpy(), it.copy())
+    dec.close()
+    (Xd, itd), (Xp, itp) = out["1"], out["0"]
+    assert len(set(itp.tolist())) > 10  # the columns stop at many different steps
+    itd, itp = itd.astype(int), itp.astype(int)
+    assert itd.sum() <= 1.01 * itp.sum() and itp.sum() <= 1.01 * itd.sum()
+    assert np.all(np.abs(itd - itp) <= 0.05 * itp + 2)
+    nb = np.linalg.norm(rhs, axis=0)
+    for Xs in (Xd, Xp):
+        floor = 50 * 2.2e-16 * float(abs(Ad).sum(axis=1).max()) * np.linalg.norm(Xs, axis=0) / nb
+        res = np.linalg.norm(rhs - Ad @ Xs, axis=0) / nb
+        assert np.all(res <= 1.5 * tol + floor)
+
+
 def test_level0_tiling_engaged(torch_cuda, capfd, monkeypatch):
     """The tiled SpMM is what runs on a graph with coordinates (the build log
     reports the timed tile shapes and the one in use)."""
