@@ -127,6 +127,50 @@ __device__ inline void grid_sum2(Ctx& c, double p1, double p2, double* sh, doubl
   c.slot ^= 1;
 }
 
+// Four grid sums sharing one barrier; sh4 holds 4 * kThreads / kWave + 4
+// doubles.  Thread 0 publishes the block's four partials (the thread that
+// releases the barrier), slot regions of 4 * nblk doubles alternate.
+__device__ inline void grid_sum4(Ctx& c, double p0, double p1, double p2, double p3,
+                                 double* sh4, double (&s)[4]) {
+  constexpr int W = kThreads / kWave;
+  double v[4] = {p0, p1, p2, p3};
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m] += __shfl_xor(v[m], off, kWave);
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) sh4[m * W + w] = v[m];
+  __syncthreads();
+  double* r = c.red + (size_t)c.slot * 4 * c.nblk;
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      double t = 0.0;
+      for (int q = 0; q < W; ++q) t += sh4[m * W + q];
+      r[(size_t)m * c.nblk + c.blk] = t;
+    }
+  grid_barrier(c);
+  if (threadIdx.x < kWave) {
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = threadIdx.x; j < c.nblk; j += kWave)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) t[m] += r[(size_t)m * c.nblk + j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) t[m] += __shfl_xor(t[m], off, kWave);
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) sh4[4 * W + m] = t[m];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < 4; ++m) s[m] = sh4[4 * W + m];
+  c.slot ^= 1;
+}
+
 // Rows handled by one wave per pass: kUnroll row-groups of kWave / lpr rows,
 // their gathers interleaved so a wave keeps several loads in flight.
 constexpr int kUnroll = 4;
@@ -369,10 +413,19 @@ __device__ inline void body_pcg1(const Pcg1Args& a, const int gblk, const int gn
 // the contiguous rows [part[bx], part[bx+1]) (balanced by nonzeros + rows on
 // the host) and keeps their slice of the matrix in LDS for the whole solve;
 // thread t owns local rows t, t + 1024, ... and holds x, r, p, q of those rows
-// in registers.  Only r goes through global memory, because neighbouring rows
-// of other blocks gather it.  The arithmetic per iteration is that of k_pcg1's
-// plain CG (q = A r + beta q, p = r + beta p, one grid sum each for p.q and
-// r.r); the sums inside a row are taken in a different order.
+// in registers.  CG with one grid barrier per iteration: an iteration first
+// applies the previous step's update to its own rows (x += alpha p,
+// r -= alpha q), forms A r gathering the neighbours' new r as r_j - alpha q_j
+// from the previous iteration's copies of r and q in global memory, updates
+// p = r + beta p, q = A r + beta q, writes r and q to the other buffer pair,
+// and ends in one grid sum of p.q, r.q, q.q and r.r.  alpha = r.r / p.q, and
+// the next residual norm, needed for beta and the stop test before the next
+// update is applied, is |r - alpha q|^2 = r.r - 2 alpha r.q + alpha^2 q.q.
+// The buffer pairs alternate, so the one barrier both publishes an
+// iteration's r and q and ends every read of the pair the next iteration
+// overwrites.  The iterates are those of plain CG; the expansion differs from
+// the summed norm by rounding relative to the previous r.r (it is not
+// trusted to stop the solve below 64 eps of it; the next direct r.r is).
 constexpr int kMaxU = 4;  // rows per thread
 
 // (A r)_i of local row l with r_i = ri (edge form when ldg != null).
@@ -399,9 +452,37 @@ __device__ inline double row_res(int l, double ri, const int* lrp, const int* lc
   return a0 + a1;
 }
 
+// (A r')_i of local row l with r'_i = ri and the neighbours' r'_j formed as
+// r_j - al q_j (the same fused multiply-add as the owner's update of r_j).
+__device__ inline double row_res_pend(int l, double ri, const int* lrp, const int* lcol,
+                                      const double* lval, const double* ldg,
+                                      const double* r, const double* q, double al) {
+  const int lo = lrp[l], hi = lrp[l + 1];
+  double a0 = 0.0, a1 = 0.0;
+  int k = lo;
+  auto g = [&](int j) { return __builtin_fma(-al, q[j], r[j]); };
+  if (ldg) {
+    for (; k + 3 < hi; k += 4) {
+      const double x0 = g(lcol[k]), x1 = g(lcol[k + 1]), x2 = g(lcol[k + 2]), x3 = g(lcol[k + 3]);
+      a0 += lval[k] * (ri - x0) + lval[k + 1] * (ri - x1);
+      a1 += lval[k + 2] * (ri - x2) + lval[k + 3] * (ri - x3);
+    }
+    for (; k < hi; ++k) a0 += lval[k] * (ri - g(lcol[k]));
+    return ldg[l] * ri + (a0 + a1);
+  }
+  for (; k + 3 < hi; k += 4) {
+    const double x0 = g(lcol[k]), x1 = g(lcol[k + 1]), x2 = g(lcol[k + 2]), x3 = g(lcol[k + 3]);
+    a0 += lval[k] * x0 + lval[k + 1] * x1;
+    a1 += lval[k + 2] * x2 + lval[k + 3] * x3;
+  }
+  for (; k < hi; ++k) a0 += lval[k] * g(lcol[k]);
+  return a0 + a1;
+}
+
 __device__ inline void body_cg1_res(const Pcg1Args& a, const int* __restrict__ part,
                                     const int gblk, const int gnb, double* lds) {
   __shared__ double sh[kThreads / kWave];
+  __shared__ double sh4[4 * kThreads / kWave + 4];
   const int bx = (gnb % 8) ? (int)gblk
                                  : (int)((gblk % 8) * (gnb / 8) + gblk / 8);
   Ctx c{a.bar, 0u, (int)gnb, (int)gblk, 0, 0, 0, 0, (int)(threadIdx.x & (kWave - 1)),
@@ -461,56 +542,74 @@ __device__ inline void body_cg1_res(const Pcg1Args& a, const int* __restrict__ p
   const double tol2 = a.tol * a.tol * bn2;
   int it = 0, flag = 0;
   bool done = !(bn2 > 0.0) || rr2 <= tol2;
-  double rho = rr2, beta = 0.0;
+  // r and q copies read by the neighbours: iteration t reads pair t % 2 and
+  // writes pair (t + 1) % 2 (a.r holds the initial residual)
+  double* rb[2] = {a.r, a.z};
+  double* qb[2] = {a.q, a.p};
+  int cur = 0;
+  double beta = 0.0, al = 0.0;  // al: the step length still to be applied
   bool first = true;
   while (!done) {
-    double ppq = 0.0;
+    const double* rin = rb[cur];
+    const double* qin = qb[cur];
+    double* rout = rb[cur ^ 1];
+    double* qout = qb[cur ^ 1];
+    double spq = 0.0, srq = 0.0, sqq = 0.0, srr = 0.0;
 #pragma unroll
     for (int u = 0; u < kMaxU; ++u) {
       const int l = threadIdx.x + u * kThreads;
       if (l < nr) {
-        const double w = row_res(l, rr_[u], lrp, lcol, lval, dg, r);
-        const double pn = first ? rr_[u] : rr_[u] + beta * pr[u];
+        double ri, w;
+        if (first) {
+          ri = rr_[u];
+          w = row_res(l, ri, lrp, lcol, lval, dg, rin);
+        } else {
+          xr[u] = __builtin_fma(al, pr[u], xr[u]);
+          ri = __builtin_fma(-al, qr[u], rr_[u]);
+          w = row_res_pend(l, ri, lrp, lcol, lval, dg, rin, qin, al);
+        }
+        const double pn = first ? ri : ri + beta * pr[u];
         const double qn = first ? w : w + beta * qr[u];
+        rr_[u] = ri;
         pr[u] = pn;
         qr[u] = qn;
-        ppq += pn * qn;
+        rout[r0 + l] = ri;
+        qout[r0 + l] = qn;
+        spq += pn * qn;
+        srq += ri * qn;
+        sqq += qn * qn;
+        srr += ri * ri;
       }
     }
     first = false;
-    const double pq = grid_sum(c, ppq, sh);
+    double sum[4];
+    grid_sum4(c, spq, srq, sqq, srr, sh4, sum);
+    cur ^= 1;
+    const double pq = sum[0], rq = sum[1], qq = sum[2], rr = sum[3];
+    al = 0.0;
+    rr2 = rr;
+    if (rr <= tol2) break;  // the update just applied met the tolerance
     if (!(pq > 0.0)) {
       flag = 1;
       break;
     }
-    const double al = rho / pq;
-    double prr = 0.0;
-#pragma unroll
-    for (int u = 0; u < kMaxU; ++u) {
-      const int l = threadIdx.x + u * kThreads;
-      if (l < nr) {
-        xr[u] += al * pr[u];
-        const double ri = rr_[u] - al * qr[u];
-        rr_[u] = ri;
-        r[r0 + l] = ri;
-        prr += ri * ri;
-      }
-    }
-    const double rn = grid_sum(c, prr, sh);
+    al = rr / pq;
     ++it;
-    beta = rn / rho;
-    rho = rn;
-    rr2 = rn;
-    if (rn <= tol2) break;
+    const double rn = rr - 2.0 * al * rq + al * al * qq;
+    const double rp = rn > 0.0 ? rn : 0.0;
+    rr2 = rp;
+    if (rn >= 64.0 * 2.220446049250313e-16 * rr && rn <= tol2) break;
     if (it >= a.maxit) {
       flag = 2;
       break;
     }
+    beta = rp / rr;
   }
+  // the last step's update of x (r is not needed any more)
 #pragma unroll
   for (int u = 0; u < kMaxU; ++u) {
     const int l = threadIdx.x + u * kThreads;
-    if (l < nr) a.x[r0 + l] = xr[u];
+    if (l < nr) a.x[r0 + l] = __builtin_fma(al, pr[u], xr[u]);
   }
   if (bx == 0 && threadIdx.x == 0) {
     a.out[0] = it;
@@ -1007,6 +1106,6 @@ void pcg1_plan_flex(const CsrView& A, const std::vector<int>& rpa, const CsrView
   plan.resident = true;
 }
 
-size_t pcg1_red_size() { return 4 * (size_t)1024; }
+size_t pcg1_red_size() { return 8 * (size_t)1024; }
 
 }  // namespace mmd
