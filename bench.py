@@ -158,14 +158,19 @@ def kernel_roofline(stats):
                 avg_launch_us=round(1000.0 * ms_tot / max(launches, 1), 2))
 
 
-def kernel_source_sha(path):
-    """SHA-256 of the dominant kernel's source text: the LDS-staged tiled SpMM
-    (its leading comment, the kernel template and its launcher) in kernels.hip."""
+CG_TILE_REGION = ("// One block-CG step on the tiled level-0 edge form with the previous step's",
+                  "int launch_cg_tile(")
+
+
+def kernel_source_sha(path, region=CG_TILE_REGION):
+    """SHA-256 of the dominant kernel's source text in kernels.hip: from the
+    kernel's leading comment through the end of its launcher (the function
+    that region[1] opens)."""
     import hashlib
     with open(path) as f:
         text = f.read()
-    i = text.index("// LDS-staged block SpMM on the tiled level-0 edge form")
-    j = text.index("int launch_spmm_tile(", i)
+    i = text.index(region[0])
+    j = text.index(region[1], i)
     j = text.index("\n}\n", j) + 3
     return hashlib.sha256(text[i:j].encode()).hexdigest()
 
@@ -174,11 +179,11 @@ def measured_traffic():
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     counter summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None
     when the kernel's source has changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "spmm_tile_rgg_n1e5_traffic.json")
+    path = os.path.join(ROOT, "profiles", "cg_tile_rgg_n1e5_traffic.json")
     try:
         with open(path) as f:
             d = json.load(f)
-        sha = kernel_source_sha(os.path.join(ROOT, d["source"]))
+        sha = kernel_source_sha(os.path.join(ROOT, d["source"]), tuple(d["source_region"]))
     except (OSError, ValueError, KeyError):
         return None
     if sha != d["source_sha256"]:
@@ -525,7 +530,7 @@ def main():
     norm_inf = float(abs(A).sum(axis=1).max())
     ncomp_null = int(np.sum(np.abs(lam - 1e-6) <= 2.0 ** -52 * norm_inf))
 
-    # dominant kernel: the level-0 fused SpMM of the refinement block CG, timed by
+    # dominant kernel: the level-0 block-CG step of the refinement (k_cg_tile), timed by
     # the library with HIP events on the solve's stream over the timed steps
     kr = kernel_roofline(stats)
     fp32 = a.precision == "fp32-refine"
@@ -533,9 +538,10 @@ def main():
         None if fp32 else measured_traffic())
     roof = {"bound": "hbm",
             "kernel": ("k_spmm32_tile: level-0 FP32 block-CG step (LDS-staged tiles)" if fp32 else
-                       "k_spmm_tile<fuse> (LDS-staged tiles of up to 32 rows touching up to "
-                       "64 rows; k_spmm_r64 when the level is not tiled): level-0 block-CG "
-                       "step P = R + beta P, Q = A R + beta Q, partial p.q") +
+                       "k_cg_tile<pending> (LDS-staged tiles of up to 32 rows touching up to "
+                       "64 rows): level-0 block-CG step with the previous step's update "
+                       "folded in: X += a P, R -= a Q, P = R + beta P, Q = A R + beta Q, "
+                       "partials p.q, r.q, q.q, r.r") +
                       " (block width %d..1)" % a.nev,
             "achieved": kr["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": kr["frac"], "traffic": traffic,

@@ -28,20 +28,21 @@ def test_traffic_follows_the_committed_counters(tmp_path, monkeypatch):
     text hashes to the value recorded with the counters; edits elsewhere in
     the file leave it valid."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "spmm_tile_rgg_n1e5_traffic.json")
+    name = "cg_tile_rgg_n1e5_traffic.json"
+    path = os.path.join(ROOT, "profiles", name)
     with open(path) as f:
         d = json.load(f)
+    start, launcher = d["source_region"]
     fake = tmp_path / "profiles"
     fake.mkdir()
     src = tmp_path / d["source"]
     src.parent.mkdir(parents=True)
-    region = ("// LDS-staged block SpMM on the tiled level-0 edge form (stand-in)\n"
-              "int launch_spmm_tile(int x) {\n  return x;\n}\n")
+    region = start + " (stand-in)\n" + launcher + "int x) {\n  return x;\n}\n"
     body = "// other kernels\n" + region + "// more kernels\n"
     src.write_text(body)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     d["source_sha256"] = hashlib.sha256(region.encode()).hexdigest()
-    (fake / "spmm_tile_rgg_n1e5_traffic.json").write_text(json.dumps(d))
+    (fake / name).write_text(json.dumps(d))
     want = round(1024.0 * (d["fetch_size_kib_per_launch"] * d["fetch_scale"] +
                            d["write_size_kib_per_launch"] * d["write_scale"]))
     assert bench.measured_traffic() == want and want > 0
@@ -52,8 +53,9 @@ def test_traffic_follows_the_committed_counters(tmp_path, monkeypatch):
     src.write_text(body.replace("return x;", "return x + 1;"))
     assert bench.measured_traffic() is None
     # the committed summary matches the kernel source in the tree
-    assert bench.kernel_source_sha(os.path.join(ROOT, d["source"])) == json.load(
-        open(path))["source_sha256"]
+    assert bench.kernel_source_sha(os.path.join(ROOT, d["source"]), (start, launcher)) == \
+        json.load(open(path))["source_sha256"]
+    assert (start, launcher) == bench.CG_TILE_REGION
 
 
 def test_cpu_sample_is_a_window_of_the_same_cloud():
