@@ -33,7 +33,7 @@ struct Ctx {
   unsigned* bar;  // arrival counter, zero at launch
   unsigned gen;   // barriers passed so far
   int nblk, blk, gtid, gsize, gwave, nwave, lane;
-  double* red;   // two disjoint slots of 2*nblk partial sums
+  double* red;   // two disjoint slots of 4*nblk partial sums
   int slot;
 };
 
@@ -75,7 +75,9 @@ __device__ inline double block_sum(double v, double* sh) {
 // adds the partials in the same fixed order.
 __device__ inline double grid_sum(Ctx& c, double part, double* sh) {
   const double b = block_sum(part, sh);
-  double* r = c.red + (size_t)c.slot * 2 * c.nblk;  // slot regions are disjoint
+  // every grid sum uses slot regions of 4 nblk doubles (the widest sum's), so
+  // consecutive sums, which take alternate slots, never share partials
+  double* r = c.red + (size_t)c.slot * 4 * c.nblk;
   if (threadIdx.x == 0) r[c.blk] = b;
   grid_barrier(c);
   // the first wavefront adds the partials (same order in every block) and
@@ -99,7 +101,7 @@ __device__ inline void grid_sum2(Ctx& c, double p1, double p2, double* sh, doubl
                                  double& s2) {
   const double b1 = block_sum(p1, sh);
   const double b2 = block_sum(p2, sh);
-  double* r = c.red + (size_t)c.slot * c.nblk * 2;
+  double* r = c.red + (size_t)c.slot * 4 * c.nblk;
   if (threadIdx.x == 0) {
     r[c.blk] = b1;
     r[c.nblk + c.blk] = b2;
@@ -244,8 +246,7 @@ __device__ inline double dir_step(Ctx& c, const CsrView& A, int lpr, const doubl
   return part;
 }
 
-__device__ inline void body_pcg1(const Pcg1Args& a, const int gblk, const int gnb) {
-  __shared__ double sh[kThreads / kWave];
+__device__ inline void body_pcg1(const Pcg1Args& a, const int gblk, const int gnb, double* sh) {
   // rows are dealt per XCD-contiguous block number (workgroups go round-robin to XCDs)
   const int bx = (gnb % 8) ? (int)gblk
                                  : (int)((gblk % 8) * (gnb / 8) + gblk / 8);
@@ -480,9 +481,8 @@ __device__ inline double row_res_pend(int l, double ri, const int* lrp, const in
 }
 
 __device__ inline void body_cg1_res(const Pcg1Args& a, const int* __restrict__ part,
-                                    const int gblk, const int gnb, double* lds) {
-  __shared__ double sh[kThreads / kWave];
-  __shared__ double sh4[4 * kThreads / kWave + 4];
+                                    const int gblk, const int gnb, double* lds, double* sh,
+                                    double* sh4) {
   const int bx = (gnb % 8) ? (int)gblk
                                  : (int)((gblk % 8) * (gnb / 8) + gblk / 8);
   Ctx c{a.bar, 0u, (int)gnb, (int)gblk, 0, 0, 0, 0, (int)(threadIdx.x & (kWave - 1)),
@@ -623,13 +623,14 @@ __device__ inline void body_cg1_res(const Pcg1Args& a, const int* __restrict__ p
 // ---------------------------------------------------------------------------
 // Resident flexible PCG (levels k >= 1): the block's rows of A^(k) and M^(k)
 // both live in LDS, the row state (x, r, z, z_old, p, q and the inner
-// ri, pi, qi) in registers; only z (gathered by A z) and ri (gathered by
-// M ri) go through global memory.  Coarse rows hold tens of entries, so
-// kLpr lanes share a row (strided over its entries, combined with xor
-// shuffles); every lane of the group keeps the row's state, lane 0 of the
-// group writes it out and contributes it to the dot products.  Same
-// arithmetic as k_pcg1's flexible branch: Polak-Ribiere beta, inner CG on M
-// from zero to tol_in ||r||.
+// ri, pi, qi) in registers; only z (gathered by A z) and the inner ri and
+// qi (gathered by M ri, double-buffered) go through global memory.  Coarse
+// rows hold tens of entries, so kLpr lanes share a row (strided over its
+// entries, combined with xor shuffles); every lane of the group keeps the
+// row's state, lane 0 of the group writes it out and contributes it to the
+// dot products.  Same method as k_pcg1's flexible branch: Polak-Ribiere
+// beta, inner CG on M from zero to tol_in ||r||, the inner CG with one grid
+// barrier per iteration (below).
 constexpr int kLpr = 8;
 constexpr int kSlots = kThreads / kLpr;  // rows per pass
 constexpr int kMaxU2 = 2;                // passes: rows per block <= 256
@@ -645,9 +646,25 @@ __device__ inline double row_lpr(bool ok, int l, int sub, const int* lrp, const 
   return acc;
 }
 
+// (B x')_l with x'_j = x_j - al q_j (the same fused multiply-add as the row
+// owner's update of x_j)
+__device__ inline double row_lpr_pend(bool ok, int l, int sub, const int* lrp, const int* lcol,
+                                      const double* lval, const double* x, const double* q,
+                                      double al) {
+  double acc = 0.0;
+  if (ok)
+    for (int k = lrp[l] + sub; k < lrp[l + 1]; k += kLpr) {
+      const int j = lcol[k];
+      acc += lval[k] * __builtin_fma(-al, q[j], x[j]);
+    }
+#pragma unroll
+  for (int off = 1; off < kLpr; off <<= 1) acc += __shfl_xor(acc, off, kWave);
+  return acc;
+}
+
 __device__ inline void body_pcg1_res(const Pcg1Args& a, const int* __restrict__ part,
-                                     const int gblk, const int gnb, double* lds) {
-  __shared__ double sh[kThreads / kWave];
+                                     const int gblk, const int gnb, double* lds, double* sh,
+                                     double* sh4) {
   const int bx = (gnb % 8) ? (int)gblk
                                  : (int)((gblk % 8) * (gnb / 8) + gblk / 8);
   Ctx c{a.bar, 0u, (int)gnb, (int)gblk, 0, 0, 0, 0, (int)(threadIdx.x & (kWave - 1)),
@@ -679,7 +696,6 @@ __device__ inline void body_pcg1_res(const Pcg1Args& a, const int* __restrict__ 
   const int sub = threadIdx.x % kLpr, slot = threadIdx.x / kLpr;
   const bool lead = sub == 0;
   double* zg = a.z;    // gathered by A z
-  double* rig = a.ri;  // gathered by M ri
   double x[kMaxU2], r[kMaxU2], z[kMaxU2], zo[kMaxU2], p[kMaxU2], q[kMaxU2];
   double ri[kMaxU2], pi[kMaxU2], qi[kMaxU2];
   bool ok[kMaxU2];
@@ -718,52 +734,75 @@ __device__ inline void body_pcg1_res(const Pcg1Args& a, const int* __restrict__ 
   int it = 0, inner_total = 0, flag = 0;
   bool done = !(bn2 > 0.0) || rr2 <= tol2;
   // z = M^-1 r approximately (inner CG from zero); z ends in registers and zg
+  // z = M^-1 r approximately (inner CG from zero); z ends in registers and zg.
+  // One grid barrier per inner iteration, as in the level-0 resident CG: an
+  // iteration applies the previous step to its own rows, gathers the
+  // neighbours' new ri as ri_j - al qi_j from the previous iteration's copies
+  // (ri and qi double-buffered), and ends in one grid sum of p.q, r.q, q.q
+  // and r.r; the next r.r for beta and the stop test is expanded from them.
+  double* rib[2] = {a.ri, a.pi};
+  double* qib[2] = {a.qi, a.q};
   auto inner = [&](double rnorm2) {
 #pragma unroll
     for (int u = 0; u < kMaxU2; ++u) {
       z[u] = 0.0;
       ri[u] = r[u];
-      if (ok[u] && lead) rig[r0 + lrow[u]] = ri[u];
+      if (ok[u] && lead) rib[0][r0 + lrow[u]] = ri[u];
     }
     grid_barrier(c);
-    double rri = rnorm2, bi = 0.0;
+    const double stop_in = tol_in2 * rnorm2;
+    double bi = 0.0, al = 0.0;  // al: the step length still to be applied
     bool f = true;
-    int k = 0;
-    while (rri > tol_in2 * rnorm2 && k < a.maxit_in) {
-      double ppq = 0.0;
+    int k = 0, cur = 0;
+    if (rnorm2 > stop_in && k < a.maxit_in) {
+      while (true) {
+        const double* rin = rib[cur];
+        const double* qin = qib[cur];
+        double* rout = rib[cur ^ 1];
+        double* qout = qib[cur ^ 1];
+        double spq = 0.0, srq = 0.0, sqq = 0.0, srr = 0.0;
 #pragma unroll
-      for (int u = 0; u < kMaxU2; ++u) {
-        const double w = row_lpr(ok[u], lrow[u], sub, mrp, mcol, mval, rig);
-        if (ok[u]) {
-          pi[u] = f ? ri[u] : ri[u] + bi * pi[u];
-          qi[u] = f ? w : w + bi * qi[u];
-          if (lead) ppq += pi[u] * qi[u];
-        }
-      }
-      f = false;
-      const double pq = grid_sum(c, ppq, sh);
-      if (!(pq > 0.0)) break;
-      const double al = rri / pq;
-      double prr = 0.0;
-#pragma unroll
-      for (int u = 0; u < kMaxU2; ++u) {
-        if (ok[u]) {
-          z[u] += al * pi[u];
-          ri[u] -= al * qi[u];
-          if (lead) {
-            rig[r0 + lrow[u]] = ri[u];
-            prr += ri[u] * ri[u];
+        for (int u = 0; u < kMaxU2; ++u) {
+          if (!f && ok[u]) {
+            z[u] = __builtin_fma(al, pi[u], z[u]);
+            ri[u] = __builtin_fma(-al, qi[u], ri[u]);
+          }
+          const double w = f ? row_lpr(ok[u], lrow[u], sub, mrp, mcol, mval, rin)
+                             : row_lpr_pend(ok[u], lrow[u], sub, mrp, mcol, mval, rin, qin, al);
+          if (ok[u]) {
+            pi[u] = f ? ri[u] : ri[u] + bi * pi[u];
+            qi[u] = f ? w : w + bi * qi[u];
+            if (lead) {
+              rout[r0 + lrow[u]] = ri[u];
+              qout[r0 + lrow[u]] = qi[u];
+              spq += pi[u] * qi[u];
+              srq += ri[u] * qi[u];
+              sqq += qi[u] * qi[u];
+              srr += ri[u] * ri[u];
+            }
           }
         }
+        f = false;
+        double sum[4];
+        grid_sum4(c, spq, srq, sqq, srr, sh4, sum);
+        cur ^= 1;
+        const double pq = sum[0], rq = sum[1], qq = sum[2], rr = sum[3];
+        al = 0.0;
+        if (rr <= stop_in) break;
+        if (!(pq > 0.0)) break;
+        al = rr / pq;
+        ++k;
+        const double rn = rr - 2.0 * al * rq + al * al * qq;
+        if (rn >= 64.0 * 2.220446049250313e-16 * rr && rn <= stop_in) break;
+        if (k >= a.maxit_in) break;
+        bi = (rn > 0.0 ? rn : 0.0) / rr;
       }
-      const double rn = grid_sum(c, prr, sh);
-      bi = rn / rri;
-      rri = rn;
-      ++k;
     }
 #pragma unroll
-    for (int u = 0; u < kMaxU2; ++u)
+    for (int u = 0; u < kMaxU2; ++u) {
+      if (ok[u]) z[u] = __builtin_fma(al, pi[u], z[u]);  // the last step's update
       if (ok[u] && lead) zg[r0 + lrow[u]] = z[u];
+    }
     inner_total += k;
   };
   if (!done) {
@@ -837,18 +876,29 @@ __device__ inline void body_pcg1_res(const Pcg1Args& a, const int* __restrict__ 
   }
 }
 
+// Static LDS of the bodies, declared once per kernel and handed down, so a
+// batched launch that may run any body holds one copy: the block-sum slots
+// (sh) and the four-way sum slots plus their results (sh4).
+constexpr int kSh = kThreads / kWave;
+constexpr int kSh4 = 4 * kThreads / kWave + 4;
+
 __global__ __launch_bounds__(kThreads) void k_pcg1(Pcg1Args a) {
-  body_pcg1(a, (int)blockIdx.x, (int)gridDim.x);
+  __shared__ double sh[kSh];
+  body_pcg1(a, (int)blockIdx.x, (int)gridDim.x, sh);
 }
 
 __global__ __launch_bounds__(kThreads) void k_cg1_res(Pcg1Args a, const int* __restrict__ part) {
   extern __shared__ double lds[];
-  body_cg1_res(a, part, (int)blockIdx.x, (int)gridDim.x, lds);
+  __shared__ double sh[kSh];
+  __shared__ double sh4[kSh4];
+  body_cg1_res(a, part, (int)blockIdx.x, (int)gridDim.x, lds, sh, sh4);
 }
 
 __global__ __launch_bounds__(kThreads) void k_pcg1_res(Pcg1Args a, const int* __restrict__ part) {
   extern __shared__ double lds[];
-  body_pcg1_res(a, part, (int)blockIdx.x, (int)gridDim.x, lds);
+  __shared__ double sh[kSh];
+  __shared__ double sh4[kSh4];
+  body_pcg1_res(a, part, (int)blockIdx.x, (int)gridDim.x, lds, sh, sh4);
 }
 
 // Several independent single-vector solves in one cooperative launch: request
@@ -859,17 +909,19 @@ __global__ __launch_bounds__(kThreads) void k_pcg1_res(Pcg1Args a, const int* __
 __global__ __launch_bounds__(kThreads) void k_pcg1_multi(const Pcg1Req* __restrict__ reqs,
                                                          int nreq) {
   extern __shared__ double lds[];
+  __shared__ double sh[kSh];
+  __shared__ double sh4[kSh4];
   int r = 0;
   while (r + 1 < nreq && (int)blockIdx.x >= reqs[r + 1].off) ++r;
   const Pcg1Req& q = reqs[r];
   const int gblk = (int)blockIdx.x - q.off;
   if (gblk >= q.nblk) return;  // padding to a whole XCD round: not part of the solve
   if (q.kind == 0)
-    body_cg1_res(q.a, q.part, gblk, q.nblk, lds);
+    body_cg1_res(q.a, q.part, gblk, q.nblk, lds, sh, sh4);
   else if (q.kind == 1)
-    body_pcg1_res(q.a, q.part, gblk, q.nblk, lds);
+    body_pcg1_res(q.a, q.part, gblk, q.nblk, lds, sh, sh4);
   else
-    body_pcg1(q.a, gblk, q.nblk);
+    body_pcg1(q.a, gblk, q.nblk, sh);
 }
 
 int lanes_for(double avg) {
