@@ -883,6 +883,41 @@ __device__ inline double col_sum(const double* __restrict__ p, int nblk, int b, 
   return r;
 }
 
+// Four column sums at once (arrays ps apart): each thread adds its slices of
+// all four, the four slices of a column inside a wavefront combine by
+// shuffles, and 16 threads add the 16 wavefronts' results.  Valid in threads
+// below kScCols.
+__device__ inline void col_sum4(const double* __restrict__ p, size_t ps, int nblk, int b,
+                                bool want, double (&out)[4]) {
+  constexpr int W = kScThreads / 64;
+  __shared__ double sh4[4 * W * kScCols];
+  const int c = blockIdx.x * kScCols + threadIdx.x % kScCols;
+  const int sl = threadIdx.x / kScCols;
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  if (want && c < b)
+    for (int q = sl; q < nblk; q += kScSlices)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) t[m] += p[m * ps + (size_t)q * b + c];
+  // lanes l, l ^ 16, l ^ 32, l ^ 48 of a wavefront hold slices of one column
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    t[m] += __shfl_xor(t[m], 16, 64);
+    t[m] += __shfl_xor(t[m], 32, 64);
+  }
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (lane < kScCols)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) sh4[(m * W + w) * kScCols + lane] = t[m];
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    out[m] = 0.0;
+    if (threadIdx.x < kScCols)
+      for (int v = 0; v < W; ++v) out[m] += sh4[(m * W + v) * kScCols + threadIdx.x];
+  }
+  __syncthreads();
+}
+
 inline int sc_grid(int b) { return ceil_div(b, kScCols); }
 
 __device__ inline int sc_col() { return blockIdx.x * kScCols + threadIdx.x; }
@@ -981,10 +1016,9 @@ __global__ __launch_bounds__(kScThreads) void k_cg_defer_scalars(ColScalars sc,
                                                                  size_t pstride, int nblk,
                                                                  int b) {
   const bool act = col_active(sc, b);
-  const double pq = col_sum(part, nblk, b, act);
-  const double rq = col_sum(part + pstride, nblk, b, act);
-  const double qq = col_sum(part + 2 * pstride, nblk, b, act);
-  const double rr = col_sum(part + 3 * pstride, nblk, b, act);
+  double sum[4];
+  col_sum4(part, pstride, nblk, b, act, sum);
+  const double pq = sum[0], rq = sum[1], qq = sum[2], rr = sum[3];
   const int c = sc_col();
   if (threadIdx.x >= kScCols || c >= b) return;
   sc.alpha[c] = 0.0;

@@ -1084,9 +1084,10 @@ void install_tiles(const TileSet& T, int kind, LevelDev& D, hipStream_t s) {
 }
 
 // Build-time autotuning of the tile shape: every shape whose tiling exists is
-// installed in turn and timed with HIP events on the fused block-CG step at
-// 256 columns (one warm-up and three timed launches on zero data; the
-// kernels' time does not depend on the values), and the fastest is kept.
+// installed in turn and timed with HIP events on the level-0 block-CG step
+// with the folded update (k_cg_tile) at 256 columns (one warm-up and three
+// timed launches on zero data; the kernels' time does not depend on the
+// values), and the fastest is kept.
 // MMDEIG_TILE=<k> forces shape k.
 void build_tiles(const HostCSR& W, LevelDev& D, hipStream_t s) {
   const int n = W.n_rows;
@@ -1105,21 +1106,32 @@ void build_tiles(const HostCSR& W, LevelDev& D, hipStream_t s) {
   std::vector<double> us(kNumTileShapes, -1.0);
   int best = cand[0];
   if (cand.size() > 1) {
+    // the kernel timed is the one the level-0 block CG spends its time in:
+    // the step with the previous update folded in (the plain fused SpMM when
+    // tiles are switched off for it)
     const int b = 256;
-    DBuf<double> X((size_t)n * b), Y((size_t)n * b), P((size_t)n * b), beta(b),
-        part((size_t)kRedBlocks * b);
-    MMD_HIP(hipMemsetAsync(X.p, 0, sizeof(double) * (size_t)n * b, s));
-    MMD_HIP(hipMemsetAsync(Y.p, 0, sizeof(double) * (size_t)n * b, s));
-    MMD_HIP(hipMemsetAsync(P.p, 0, sizeof(double) * (size_t)n * b, s));
+    const size_t nb = (size_t)n * b;
+    DBuf<double> X(nb), R(nb), Q(nb), Ra(nb), Qa(nb), P(nb), alpha(b), beta(b),
+        part((size_t)4 * kRedBlocks * b);
+    for (DBuf<double>* v : {&X, &R, &Q, &Ra, &Qa, &P})
+      MMD_HIP(hipMemsetAsync(v->p, 0, sizeof(double) * nb, s));
+    MMD_HIP(hipMemsetAsync(alpha.p, 0, sizeof(double) * b, s));
     MMD_HIP(hipMemsetAsync(beta.p, 0, sizeof(double) * b, s));
+    auto step = [&]() {
+      if (cg_tile_ok(D.A))
+        cg_tile_step(D.A, X.p, b, R.p, Q.p, Ra.p, Qa.p, P.p, b, b, true, false, alpha.p, beta.p,
+                     part.p, (size_t)kRedBlocks * b, s);
+      else
+        spmm(D.A, R.p, b, Q.p, b, b, s, true, false, beta.p, P.p, b, part.p);
+    };
     hipEvent_t e0, e1;
     MMD_HIP(hipEventCreate(&e0));
     MMD_HIP(hipEventCreate(&e1));
     for (int k : cand) {
       install_tiles(sets[k], k, D, s);
-      spmm(D.A, X.p, b, Y.p, b, b, s, true, false, beta.p, P.p, b, part.p);
+      step();
       MMD_HIP(hipEventRecord(e0, s));
-      for (int r = 0; r < 3; ++r) spmm(D.A, X.p, b, Y.p, b, b, s, true, false, beta.p, P.p, b, part.p);
+      for (int r = 0; r < 3; ++r) step();
       MMD_HIP(hipEventRecord(e1, s));
       MMD_HIP(hipEventSynchronize(e1));
       float ms = 0.f;

@@ -544,16 +544,18 @@ __device__ inline void body_cg1_res(const Pcg1Args& a, const int* __restrict__ p
   bool done = !(bn2 > 0.0) || rr2 <= tol2;
   // r and q copies read by the neighbours: iteration t reads pair t % 2 and
   // writes pair (t + 1) % 2 (a.r holds the initial residual)
-  double* rb[2] = {a.r, a.z};
-  double* qb[2] = {a.q, a.p};
+  double* const r0b = a.r;
+  double* const r1b = a.z;
+  double* const q0b = a.q;
+  double* const q1b = a.p;
   int cur = 0;
   double beta = 0.0, al = 0.0;  // al: the step length still to be applied
   bool first = true;
   while (!done) {
-    const double* rin = rb[cur];
-    const double* qin = qb[cur];
-    double* rout = rb[cur ^ 1];
-    double* qout = qb[cur ^ 1];
+    const double* rin = cur ? r1b : r0b;
+    const double* qin = cur ? q1b : q0b;
+    double* rout = cur ? r0b : r1b;
+    double* qout = cur ? q0b : q1b;
     double spq = 0.0, srq = 0.0, sqq = 0.0, srr = 0.0;
 #pragma unroll
     for (int u = 0; u < kMaxU; ++u) {
@@ -696,23 +698,25 @@ __device__ inline void body_pcg1_res(const Pcg1Args& a, const int* __restrict__ 
   const int sub = threadIdx.x % kLpr, slot = threadIdx.x / kLpr;
   const bool lead = sub == 0;
   double* zg = a.z;    // gathered by A z
-  double x[kMaxU2], r[kMaxU2], z[kMaxU2], zo[kMaxU2], p[kMaxU2], q[kMaxU2];
+  // x stays in global memory (its owner updates it once per outer step),
+  // the rest of the row state in registers
+  double r[kMaxU2], z[kMaxU2], zo[kMaxU2], p[kMaxU2], q[kMaxU2];
   double ri[kMaxU2], pi[kMaxU2], qi[kMaxU2];
   bool ok[kMaxU2];
   int lrow[kMaxU2];
   double pb = 0.0, prr0 = 0.0;
 #pragma unroll
   for (int u = 0; u < kMaxU2; ++u) {
-    x[u] = r[u] = z[u] = zo[u] = p[u] = q[u] = ri[u] = pi[u] = qi[u] = 0.0;
+    r[u] = z[u] = zo[u] = p[u] = q[u] = ri[u] = pi[u] = qi[u] = 0.0;
     lrow[u] = slot + u * kSlots;
     ok[u] = lrow[u] < nr;
     if (ok[u]) {
       const double bi = a.b[r0 + lrow[u]];
       if (lead) pb += bi * bi;
-      if (a.use_x0)
-        x[u] = a.x[r0 + lrow[u]];
-      else
+      if (!a.use_x0) {
         r[u] = bi;
+        if (lead) a.x[r0 + lrow[u]] = 0.0;  // no block gathers x without x0
+      }
     }
   }
   if (a.use_x0) {
@@ -740,14 +744,16 @@ __device__ inline void body_pcg1_res(const Pcg1Args& a, const int* __restrict__ 
   // neighbours' new ri as ri_j - al qi_j from the previous iteration's copies
   // (ri and qi double-buffered), and ends in one grid sum of p.q, r.q, q.q
   // and r.r; the next r.r for beta and the stop test is expanded from them.
-  double* rib[2] = {a.ri, a.pi};
-  double* qib[2] = {a.qi, a.q};
+  double* const ri0 = a.ri;
+  double* const ri1 = a.pi;
+  double* const qi0 = a.qi;
+  double* const qi1 = a.q;
   auto inner = [&](double rnorm2) {
 #pragma unroll
     for (int u = 0; u < kMaxU2; ++u) {
       z[u] = 0.0;
       ri[u] = r[u];
-      if (ok[u] && lead) rib[0][r0 + lrow[u]] = ri[u];
+      if (ok[u] && lead) ri0[r0 + lrow[u]] = ri[u];
     }
     grid_barrier(c);
     const double stop_in = tol_in2 * rnorm2;
@@ -756,10 +762,10 @@ __device__ inline void body_pcg1_res(const Pcg1Args& a, const int* __restrict__ 
     int k = 0, cur = 0;
     if (rnorm2 > stop_in && k < a.maxit_in) {
       while (true) {
-        const double* rin = rib[cur];
-        const double* qin = qib[cur];
-        double* rout = rib[cur ^ 1];
-        double* qout = qib[cur ^ 1];
+        const double* rin = cur ? ri1 : ri0;
+        const double* qin = cur ? qi1 : qi0;
+        double* rout = cur ? ri0 : ri1;
+        double* qout = cur ? qi0 : qi1;
         double spq = 0.0, srq = 0.0, sqq = 0.0, srr = 0.0;
 #pragma unroll
         for (int u = 0; u < kMaxU2; ++u) {
@@ -836,7 +842,7 @@ __device__ inline void body_pcg1_res(const Pcg1Args& a, const int* __restrict__ 
 #pragma unroll
       for (int u = 0; u < kMaxU2; ++u) {
         if (ok[u]) {
-          x[u] += al * p[u];
+          if (lead) a.x[r0 + lrow[u]] += al * p[u];
           r[u] -= al * q[u];
           zo[u] = z[u];
           if (lead) prr += r[u] * r[u];
@@ -864,9 +870,6 @@ __device__ inline void body_pcg1_res(const Pcg1Args& a, const int* __restrict__ 
       rz = rzn;
     }
   }
-#pragma unroll
-  for (int u = 0; u < kMaxU2; ++u)
-    if (ok[u] && lead) a.x[r0 + lrow[u]] = x[u];
   if (bx == 0 && threadIdx.x == 0) {
     a.out[0] = it;
     a.out[1] = inner_total;

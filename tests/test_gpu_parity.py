@@ -266,7 +266,8 @@ def test_level0_tiling_engaged(torch_cuda, capfd, monkeypatch):
 
 @pytest.mark.parametrize("b", [1, 4])
 def test_level_solves(built, torch_cuda, b):
-    """b = 1 runs the persistent single-vector kernel, b = 4 the block kernels."""
+    """b = 1 runs the persistent single-vector kernel (from zero and from a
+    caller's start), b = 4 the block kernels."""
     torch = torch_cuda
     p, kw, dec, M = built
     tol = 1e-10
@@ -289,6 +290,17 @@ def test_level_solves(built, torch_cuda, b):
             err = np.linalg.norm(X[:, c] - xo) / np.linalg.norm(xo)
             cond = np.linalg.cond(Ad) if lev.n <= 4096 else 1e8
             assert err <= 3 * tol * cond
+        if b == 1:
+            # warm start (x0 from the caller, as in the refinement): from the
+            # solution scaled by 1 + 1e-6 the start residual is ~1e-6 ||b||, so
+            # the solve meets the same tolerance in no more iterations, and in
+            # fewer unless the cold solve itself needs only a handful
+            Xw, itw = dec.solve(k, 0, _t(torch, rhs), x0=_t(torch, X * (1.0 + 1e-6)), tol=tol)
+            Xw = Xw.cpu().numpy()
+            floor = solve_floor(p.scipy() if k == 0 else lev.A, Xw, rhs)
+            res = np.linalg.norm(rhs - Ad @ Xw, axis=0) / nb
+            assert np.all(res <= 1.5 * tol + floor)
+            assert itw[0] <= it[0] and (it[0] <= 10 or itw[0] < it[0])
         if k < M.K:
             up = M.levels[k + 1]
             U = up.U_apply(np.eye(up.nb()))
