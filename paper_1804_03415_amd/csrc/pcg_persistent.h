@@ -21,6 +21,7 @@ struct Pcg1Args {
   double tol = 0.0, tol_in = 0.0;
   int maxit = 100000, maxit_in = 500, use_x0 = 0;
   int lpr_a = 8, lpr_m = 8;
+  int fold = 1;  // resident plain CG: one barrier per iteration (1) or two (0); from the plan
   int* out = nullptr;     // [3]: outer iterations, inner iterations, flag (1 not SPD, 2 cap)
   double* res = nullptr;  // [2]: final ||r||^2, ||b||^2
 };
@@ -30,6 +31,7 @@ struct Pcg1Args {
 struct Pcg1Plan {
   bool resident = false;
   bool flex = false;  // resident flexible PCG (A and M slices in LDS)
+  bool fold = true;   // plain CG: one barrier per iteration (most gathers block-local)
   int grid = 0;
   size_t lds = 0;
   DBuf<int> part;  // grid + 1 row boundaries

@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 
 #include "common.h"
@@ -427,6 +428,10 @@ __device__ inline void body_pcg1(const Pcg1Args& a, const int gblk, const int gn
 // overwrites.  The iterates are those of plain CG; the expansion differs from
 // the summed norm by rounding relative to the previous r.r (it is not
 // trusted to stop the solve below 64 eps of it; the next direct r.r is).
+// The second gathered vector pays off when the gathers stay mostly within a
+// block's own rows (the patch-ordered level 0); for a matrix in an order
+// that scatters them the plan selects the two-barrier form (a.fold = 0):
+// plain CG with one gathered vector, grid sums of p.q and of r.r.
 constexpr int kMaxU = 4;  // rows per thread
 
 // (A r)_i of local row l with r_i = ri (edge form when ldg != null).
@@ -551,6 +556,57 @@ __device__ inline void body_cg1_res(const Pcg1Args& a, const int* __restrict__ p
   int cur = 0;
   double beta = 0.0, al = 0.0;  // al: the step length still to be applied
   bool first = true;
+  if (!a.fold) {
+    // two grid barriers per iteration (p.q, then r.r) and one gathered vector:
+    // the plan's choice when most gathered rows belong to other blocks, where
+    // a second gathered vector costs more than the barrier it saves
+    double rho = rr2;
+    while (!done) {
+      double ppq = 0.0;
+#pragma unroll
+      for (int u = 0; u < kMaxU; ++u) {
+        const int l = threadIdx.x + u * kThreads;
+        if (l < nr) {
+          const double w = row_res(l, rr_[u], lrp, lcol, lval, dg, r0b);
+          const double pn = first ? rr_[u] : rr_[u] + beta * pr[u];
+          const double qn = first ? w : w + beta * qr[u];
+          pr[u] = pn;
+          qr[u] = qn;
+          ppq += pn * qn;
+        }
+      }
+      first = false;
+      const double pq = grid_sum(c, ppq, sh);
+      if (!(pq > 0.0)) {
+        flag = 1;
+        break;
+      }
+      const double a2 = rho / pq;
+      double prr = 0.0;
+#pragma unroll
+      for (int u = 0; u < kMaxU; ++u) {
+        const int l = threadIdx.x + u * kThreads;
+        if (l < nr) {
+          xr[u] += a2 * pr[u];
+          const double ri = rr_[u] - a2 * qr[u];
+          rr_[u] = ri;
+          r0b[r0 + l] = ri;
+          prr += ri * ri;
+        }
+      }
+      const double rn = grid_sum(c, prr, sh);
+      ++it;
+      beta = rn / rho;
+      rho = rn;
+      rr2 = rn;
+      if (rn <= tol2) break;
+      if (it >= a.maxit) {
+        flag = 2;
+        break;
+      }
+    }
+    done = true;  // al stays 0: x is complete
+  }
   while (!done) {
     const double* rin = cur ? r1b : r0b;
     const double* qin = cur ? q1b : q0b;
@@ -958,6 +1014,7 @@ Pcg1Req pcg1_request(Pcg1Args a, const Pcg1Plan* plan) {
   Pcg1Req q;
   if (plan && plan->resident && (a.M.rowptr != nullptr) == plan->flex) {
     q.kind = plan->flex ? 1 : 0;
+    a.fold = plan->fold ? 1 : 0;
     q.part = plan->part.p;
     q.nblk = plan->grid;
     q.lds = plan->lds;
@@ -1014,6 +1071,7 @@ void pcg1(Pcg1Args a, hipStream_t s, const Pcg1Plan* plan) {
   void* args[] = {&a};
   if (plan && plan->resident && (a.M.rowptr != nullptr) == plan->flex) {
     const int* part = plan->part.p;
+    a.fold = plan->fold ? 1 : 0;
     void* rargs[] = {&a, &part};
     const void* fn = plan->flex ? reinterpret_cast<const void*>(k_pcg1_res)
                                 : reinterpret_cast<const void*>(k_cg1_res);
@@ -1093,6 +1151,29 @@ void pcg1_plan(const CsrView& A, const std::vector<int>& rp, Pcg1Plan& plan, hip
   int per = 0;
   MMD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_cg1_res, kThreads, lds));
   if (per <= 0 || grid > per * cus) return;
+  // gather locality: the share of entries whose column lies in the row's own
+  // block picks the one-barrier form (at least half) or the two-barrier form
+  // (MMDEIG_CG1_FOLD=0/1 forces one)
+  {
+    std::vector<int> col(static_cast<size_t>(rp[n]));
+    if (!col.empty()) {
+      MMD_HIP(hipMemcpyAsync(col.data(), A.col, sizeof(int) * col.size(), hipMemcpyDeviceToHost,
+                             s));
+      MMD_HIP(hipStreamSynchronize(s));
+    }
+    int64_t local = 0;
+    for (int j = 0; j < grid; ++j)
+      for (int k = rp[part[j]]; k < rp[part[j + 1]]; ++k)
+        local += (col[k] >= part[j] && col[k] < part[j + 1]) ? 1 : 0;
+    plan.fold = col.empty() || 2 * local >= static_cast<int64_t>(col.size());
+    if (const char* e = std::getenv("MMDEIG_CG1_FOLD"))
+      if (e[0]) plan.fold = std::atoi(e) != 0;
+    if (const char* e = std::getenv("MMDEIG_LOG"))
+      if (std::atoi(e) != 0)
+        std::fprintf(stderr, "[mmdeig] resident CG plan: n %d, %d blocks, block-local entries %.3f, %s\n",
+                     n, grid, col.empty() ? 1.0 : static_cast<double>(local) / col.size(),
+                     plan.fold ? "one barrier per iteration" : "two barriers per iteration");
+  }
   plan.part.ensure(grid + 1);
   MMD_HIP(hipMemcpyAsync(plan.part.p, part.data(), sizeof(int) * (grid + 1),
                          hipMemcpyHostToDevice, s));
